@@ -1,0 +1,155 @@
+/*
+ * pir.h -- C ABI of the MI355X RowSel library (libpir.so).
+ *
+ * RowSel is the database-scanning stage of OnionPIR-style lattice PIR
+ * (GPIR, sec. 2.2 "RowSel"): of the D0 selector ciphertexts a client sends,
+ * every one encrypts 0 except row i*'s, which encrypts 1; the server
+ * multiplies them with the D0 x D1 plaintext database to obtain D1
+ * ciphertexts that encrypt row i*.  In the NTT domain this is, for every
+ * point p of the L*N RNS/NTT points (sec. 2.4.1) and every prime q_l,
+ * an independent matrix product mod q_l (sec. 2.3):
+ *
+ *     M_out[p][m][n] = sum_{k < D0} M_in0[p][m][k] * M_in1[p][k][n]  mod q_l
+ *
+ * with m over the 2*B ciphertext polynomials of B clients (multi-client
+ * batching, sec. 3.1), k over the DB rows and n over the DB columns.
+ *
+ * Index conventions used by every call below:
+ *   p = l*N + j      (l: prime index, j: NTT point), a polynomial is [L][N]
+ *   m = 2*b + c      (b: client, c: ciphertext component, 0 = first supplied)
+ *   query  tensor  [B][2][D0][L][N]  uint32, residues in [0, q_l)
+ *   DB     source  [D0][D1][L][N]    uint32 (coefficients or NTT values)
+ *   output tensor  [B][2][D1][L][N]  uint32, canonical residues in [0, q_l)
+ * All arrays are dense, row-major, and live in device memory unless stated.
+ *
+ * Results are exact: every output word equals the mathematical sum reduced
+ * into [0, q_l), independent of the path, tile or batch composition.
+ *
+ * Threading and streams: calls take a hipStream_t (as void*, NULL = the
+ * legacy default stream) and are asynchronous on it unless stated; the
+ * caller keeps inputs and outputs alive until the stream passes the call.
+ * A pir_db may be read by concurrent calls; loading into it must not overlap
+ * a RowSel call that reads it.
+ *
+ * Errors: every call returns pir_status; no C++ exception crosses the ABI.
+ * Argument and shape checks fail with PIR_EINVAL before anything is
+ * enqueued; pir_last_error() returns a thread-local message describing the
+ * most recent failure on the calling thread.
+ */
+#ifndef PIR_H
+#define PIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIR_OK = 0,
+    PIR_EINVAL = -1,        /* bad argument, shape or parameter */
+    PIR_ENOMEM = -2,        /* device allocation failed */
+    PIR_EDEVICE = -3,       /* a HIP runtime call failed */
+    PIR_EBUSY = -4,         /* serving: request not admitted now (capacity) */
+    PIR_EUNSUPPORTED = -5   /* valid request this build does not implement */
+} pir_status;
+
+#define PIR_MAX_PRIMES 4
+
+/* Ring and database parameters.
+ *   n       ring degree N: a power of two, 8 <= N <= 65536
+ *   nprimes L: number of RNS primes, 1..4 (the paper uses four, sec. 2.4.1)
+ *   q[l]    primes q < 2^30 with q = 1 (mod 2N) (needed for the negacyclic
+ *           NTT); the < 2^30 bound is what keeps up to fifteen 60-bit
+ *           products exact in one 64-bit accumulator
+ *   d0, d1  DB rows (selector count) and columns, each 1..65536 */
+typedef struct {
+    uint32_t n;
+    uint32_t nprimes;
+    uint32_t q[PIR_MAX_PRIMES];
+    uint32_t d0;
+    uint32_t d1;
+} pir_params;
+
+typedef enum {
+    PIR_DOMAIN_COEFF = 0,   /* source holds coefficients; the library NTTs them */
+    PIR_DOMAIN_NTT = 1      /* source already holds NTT values in natural order */
+} pir_domain;
+
+typedef enum {
+    PIR_PATH_AUTO = 0,      /* pick by batch size from the layouts present */
+    PIR_PATH_VALU = 1,      /* 32x32->64-bit integer multiply-add kernels */
+    PIR_PATH_MFMA_I8 = 2    /* exact signed 8-bit digit split on INT8 MFMA */
+} pir_path;
+
+/* Device layouts a DB can hold (bit flags for pir_db_create). Each takes
+ * L*N*D0*D1*4 bytes of HBM (the MFMA one pads D0 up to a multiple of 64). */
+#define PIR_LAYOUT_VALU 1u
+#define PIR_LAYOUT_MFMA 2u
+
+typedef struct pir_db pir_db;   /* opaque, device resident, library owned */
+
+/* Allocate an empty DB on the current HIP device.
+ * Validates every parameter (PIR_EINVAL with a message otherwise); `layouts`
+ * is a non-empty subset of PIR_LAYOUT_*.  On success *out owns the device
+ * memory until pir_db_free.  Database organisation: D0 x D1 records, each a
+ * plaintext polynomial kept in the NTT domain (sec. 2.2, sec. 6 on the
+ * NTT-domain storage); the internal layouts are transposed slot-major so
+ * RowSel reads them coalesced (sec. 5.2.1: the DB layout is free because it
+ * is transposed before any query arrives). */
+pir_status pir_db_create(const pir_params *params, uint32_t layouts, pir_db **out);
+
+/* Load DB rows [row0, row0 + nrows) from a device buffer `src_dev` laid out
+ * [nrows][D1][L][N] (uint32).  PIR_DOMAIN_COEFF: values are coefficients
+ * (any uint32; reduced mod q_l), transformed by the negacyclic NTT with
+ * natural point order ahat_i = a(psi_l^(2i+1)), psi_l = g^((q_l-1)/2N),
+ * g the smallest generator mod q_l (sec. 2.4.1).  PIR_DOMAIN_NTT: values
+ * must be residues < q_l and are taken as they are.  The source is only
+ * read; it may be freed once the stream passes the call.  Temporary device
+ * memory of nrows*D1*L*N*4 bytes is used for COEFF input. */
+pir_status pir_db_load_ntt(pir_db *db, const uint32_t *src_dev, uint32_t row0,
+                           uint32_t nrows, pir_domain domain, void *hip_stream);
+
+/* Copy the DB parameters out. */
+pir_status pir_db_params(const pir_db *db, pir_params *out);
+
+/* Layout flags actually present. */
+uint32_t pir_db_layouts(const pir_db *db);
+
+/* Release a DB (NULL is a no-op).  Synchronises the device first. */
+void pir_db_free(pir_db *db);
+
+/* RowSel for B clients against one DB (sec. 2.2, sec. 2.3, sec. 5.1.1):
+ *   out[b][c][n][l][j] = sum_k q[b][c][k][l][j] * DB_ntt[k][n][l][j] mod q_l
+ * q_dev:  [B][2][D0][L][N] residues < q_l (larger values give unspecified
+ *         results; PIR_VALIDATE=1 in the environment checks them and fails
+ *         with PIR_EINVAL instead)
+ * out_dev: [B][2][D1][L][N]; must not overlap q_dev.
+ * B = 0 is a no-op.  `path` must name a layout the DB holds (PIR_EINVAL
+ * otherwise); PIR_PATH_AUTO picks the VALU kernels for small batches and
+ * the INT8 MFMA kernels for large ones when both layouts exist. */
+pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
+                      uint32_t *out_dev, pir_path path, void *hip_stream);
+
+/* ---------------------------------------------------------------- helpers */
+/* Negacyclic NTT / inverse NTT of `count` contiguous length-n polynomials
+ * mod prime q (same convention as pir_db_load_ntt).  Not part of RowSel's
+ * hot path: used to build inputs and to check results (client-side
+ * decryption).  in_dev may equal out_dev. */
+pir_status pir_ntt_forward(const uint32_t *in_dev, uint32_t *out_dev, uint32_t count,
+                           uint32_t n, uint32_t q, void *hip_stream);
+pir_status pir_ntt_inverse(const uint32_t *in_dev, uint32_t *out_dev, uint32_t count,
+                           uint32_t n, uint32_t q, void *hip_stream);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *pir_last_error(void);
+
+/* Library version string. */
+const char *pir_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIR_H */

@@ -1,0 +1,165 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/pir.h"
+
+namespace pir {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+void clear_error();
+
+struct Error {
+    pir_status status;
+    std::string msg;
+};
+
+#define PIR_FAIL(st, ...)                                                     \
+    do {                                                                      \
+        char _buf[512];                                                       \
+        std::snprintf(_buf, sizeof(_buf), __VA_ARGS__);                       \
+        throw ::pir::Error{st, std::string(_buf)};                            \
+    } while (0)
+
+#define PIR_REQUIRE(cond, ...)                                                \
+    do {                                                                      \
+        if (!(cond)) PIR_FAIL(PIR_EINVAL, __VA_ARGS__);                       \
+    } while (0)
+
+#define PIR_HIP(call)                                                         \
+    do {                                                                      \
+        hipError_t _e = (call);                                               \
+        if (_e != hipSuccess)                                                 \
+            PIR_FAIL(PIR_EDEVICE, "%s failed: %s (%s:%d)", #call,             \
+                     hipGetErrorString(_e), __FILE__, __LINE__);              \
+    } while (0)
+
+// After a kernel launch: catches launch-configuration errors.
+#define PIR_LAUNCH_CHECK() PIR_HIP(hipGetLastError())
+
+// Runs `body` and converts exceptions into a status + thread-local message.
+template <class F>
+pir_status guarded(F &&body) {
+    try {
+        clear_error();
+        body();
+        return PIR_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PIR_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(std::string("internal error: ") + e.what());
+        return PIR_EDEVICE;
+    } catch (...) {
+        set_error("internal error");
+        return PIR_EDEVICE;
+    }
+}
+
+// --------------------------------------------------------- modular constants
+// Per-prime constants passed to kernels by value.
+//   q      the prime, < 2^30
+//   r32    2^32 mod q           (folding a 64-bit sum: hi*2^32 + lo = hi*r32 + lo)
+//   mu     floor(2^64 / q)      (Barrett reduction of a 64-bit value)
+//   moff   the largest multiple of q not above 2^63 (shifts a signed 64-bit
+//          sum of magnitude < 2^62 into [0, 2^64) without changing it mod q)
+//   w[s]   2^(8s) mod q, s = 0..6 (weights of the digit-product groups)
+struct ModQ {
+    uint32_t q;
+    uint32_t r32;
+    uint64_t mu;
+    uint64_t moff;
+    uint32_t w[7];
+    uint32_t fold2;   // 1 when r32 >= 2^28: two folds keep fifteen more products exact
+};
+
+ModQ make_modq(uint32_t q);
+bool is_prime_u32(uint32_t q);
+uint32_t pow_mod(uint64_t a, uint64_t e, uint32_t q);
+
+// Tables for the on-device negacyclic NTT of one prime.
+struct NttTables {
+    uint32_t q = 0, n = 0;
+    uint32_t *fwd = nullptr;      // [n] psi^brv(i) and Shoup companions [n]
+    uint32_t *inv = nullptr;      // [n] psi^-brv(i) and companions [n]
+    uint32_t n_inv = 0, n_inv_shoup = 0;
+};
+
+// Tables are built once per (q, n) and kept for the process lifetime.
+const NttTables &ntt_tables(uint32_t q, uint32_t n);
+
+// ------------------------------------------------------------------ the DB
+struct DbLayoutValu {
+    // [L][N/4][D0][D1][4] uint32: for a group of four consecutive NTT points
+    // of one prime, each DB row is a contiguous run of D1 16-byte vectors.
+    uint32_t *data = nullptr;
+};
+
+struct DbLayoutMfma {
+    // [L*N][4][D1][Kp] int8: per point p and digit d, column n holds the
+    // d-th signed 8-bit digit of DB[k][n] for k < D0, zero for D0 <= k < Kp.
+    int8_t *data = nullptr;
+    uint32_t kp = 0;   // D0 rounded up to a multiple of 64
+};
+
+}  // namespace pir
+
+struct pir_db {
+    pir_params p{};
+    uint32_t layouts = 0;
+    int device = 0;
+    pir::ModQ mod[PIR_MAX_PRIMES]{};
+    pir::DbLayoutValu valu;
+    pir::DbLayoutMfma mfma;
+    uint64_t slots() const { return (uint64_t)p.n * p.nprimes; }
+};
+
+namespace pir {
+
+// Validation shared by the entry points.
+void validate_params(const pir_params &p);
+
+// Device buffer that frees itself (used for temporaries).
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n);
+    ~DevBuf();
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+void *dev_alloc(size_t bytes);   // throws PIR_ENOMEM
+void dev_free(void *p);
+
+bool env_flag(const char *name);
+
+// ---------------------------------------------------------------- launchers
+// Defined in the kernel translation units; all enqueue on `st`.
+void launch_ntt(const uint32_t *in, uint32_t *out, uint64_t count, uint64_t in_stride,
+                uint64_t out_stride, const NttTables &t, bool inverse, hipStream_t st);
+void launch_db_layout_valu(const pir_db &db, const uint32_t *ntt_src, uint32_t row0,
+                           uint32_t nrows, hipStream_t st);
+void launch_db_layout_mfma(const pir_db &db, const uint32_t *ntt_src, uint32_t row0,
+                           uint32_t nrows, hipStream_t st);
+void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
+                        hipStream_t st);
+void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
+                        hipStream_t st);
+size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
+void launch_validate_residues(const uint32_t *x, uint64_t count_per_limb_block, uint32_t n,
+                              uint32_t nprimes, const uint32_t *q, uint64_t total,
+                              uint32_t *flag, hipStream_t st);
+
+}  // namespace pir

@@ -1,0 +1,88 @@
+// Device-side modular arithmetic for primes q < 2^30.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "common.h"
+
+namespace pir {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte load marked non-temporal: streamed data that is read once should
+// not displace reused lines from the caches.
+__device__ __forceinline__ uint4 ld_nt(const uint4 *p) {
+    u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// hi*2^32 + lo  ==  hi*r32 + lo  (mod q).  For x < 2^64 the result is below
+// 2^32*r32 + 2^32; a single v_mad_u64_u32.
+__device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r32) {
+    return (uint64_t)(uint32_t)(x >> 32) * r32 + (uint64_t)(uint32_t)x;
+}
+
+// Brings a lazy 64-bit sum back under 2^60 + 2^32, after which fifteen more
+// products of residues (< (2^30-1)^2 each) still fit in 64 bits:
+//   one fold suffices when r32 < 2^28 (2^32 * 2^28 + 2^32),
+//   otherwise a second fold takes the first result (< 2^62 + 2^32) there.
+__device__ __forceinline__ uint64_t lazy_fold(uint64_t x, const ModQ &m) {
+    x = fold32(x, m.r32);
+    if (m.fold2) x = fold32(x, m.r32);
+    return x;
+}
+
+// Barrett reduction of any 64-bit value into [0, q):
+// qhat = floor(x * mu / 2^64) is floor(x/q) or one less, so one correction.
+__device__ __forceinline__ uint32_t reduce64(uint64_t x, const ModQ &m) {
+    uint64_t qh = __umul64hi(x, m.mu);
+    uint64_t r = x - qh * (uint64_t)m.q;
+    return (uint32_t)(r >= m.q ? r - m.q : r);
+}
+
+// Shoup multiplication by a constant w < q with companion ws = floor(w*2^32/q):
+// a*w - floor(a*ws/2^32)*q lies in [0, 2q) for a < 2^32; one correction.
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
+    uint32_t qt = __umulhi(a, ws);
+    uint32_t r = a * w - qt * q;
+    return r >= q ? r - q : r;
+}
+
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t q) {
+    uint32_t s = a + b;
+    return s >= q ? s - q : s;
+}
+
+__device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t q) {
+    return a >= b ? a - b : a + q - b;
+}
+
+// Balanced signed base-2^8 digits of x < 2^31: x = sum_i d_i 2^(8i),
+// d_i in [-128, 127] (the top digit of x < 2^30 stays within [0, 64]).
+// Returned packed as four int8 in one 32-bit word, digit i in byte i.
+__device__ __forceinline__ uint32_t split_digits(uint32_t x) {
+    uint32_t packed = 0;
+    int32_t v = (int32_t)x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int32_t d = ((v + 128) & 255) - 128;
+        packed |= ((uint32_t)(uint8_t)(int8_t)d) << (8 * i);
+        v = (v - d) >> 8;
+    }
+    return packed;
+}
+
+// Maps blockIdx.x so that runs of consecutive logical block indices execute
+// on the same XCD (the hardware deals workgroups to the 8 XCDs round-robin),
+// keeping data that neighbouring blocks share inside one XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
+    constexpr uint32_t X = 8;
+    uint32_t per = nblocks / X, rem = nblocks % X;
+    uint32_t xcd = bid % X, r = bid / X;
+    // XCDs [0, rem) own per+1 logical blocks, the rest own per
+    uint32_t base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return base + r;
+}
+
+}  // namespace pir

@@ -1,0 +1,248 @@
+// RowSel on the vector ALUs: exact 32x32->64-bit multiply-adds (v_mad_u64_u32)
+// with lazy 64-bit accumulation.
+//
+// The operation (sec. 2.3): for each of the L*N points p and prime q_l,
+//   out[m][n] = sum_k Q[m][k] * DB[k][n] mod q_l.
+// Both kernels read the DB from the VALU layout [L][N/4][D0][D1][4]: a thread
+// owns four consecutive points of one prime (one 16-byte vector), so the
+// four independent per-point GEMMs of a group advance in lock step and each
+// DB row of a group is a contiguous run of D1 vectors (the transposed,
+// point-innermost layout that lets a wavefront stream whole rows; compare
+// the paper's transposed layout of sec. 5.2.1).  Queries and outputs are
+// read/written in the boundary layout directly: for fixed (m, k) the points
+// are contiguous there as well, so a 16-byte vector per (m, k) / (m, n)
+// needs no separate transpose pass.
+//
+// Accumulation: products of residues are < 2^60, so a 64-bit sum absorbs
+// fifteen of them on top of a folded remainder (< 2^60 + 2^32); every
+// fifteen rows the sum is folded (hi*2^32 + lo -> hi*(2^32 mod q) + lo) and
+// one Barrett reduction at the end yields the canonical residue.
+#include <algorithm>
+
+#include "common.h"
+#include "modarith.h"
+
+namespace pir {
+
+struct ModQ4 {
+    ModQ m[PIR_MAX_PRIMES];
+};
+
+__device__ __forceinline__ void mad4(uint64_t (&acc)[4], const uint4 &a, const uint4 &b) {
+    acc[0] += (uint64_t)a.x * b.x;
+    acc[1] += (uint64_t)a.y * b.y;
+    acc[2] += (uint64_t)a.z * b.z;
+    acc[3] += (uint64_t)a.w * b.w;
+}
+
+// --------------------------------------------------------------- streaming
+// Small batches (m = 2B <= 8 rows): the whole m extent lives in registers;
+// a block owns one point group and 256 consecutive columns and streams the
+// group's DB rows once.  The query vector of (m, k) is the same for every
+// lane, so it is read with scalar loads into SGPRs and feeds
+// v_mad_u64_u32 as its scalar operand: no LDS staging, no VGPRs.  This is
+// the HBM-bound regime of one client (sec. 3.1): two multiply-adds per
+// 4-byte DB word.
+constexpr int STREAM_THREADS = 256;
+constexpr int STREAM_UNROLL = 15;
+
+template <int MB>
+__global__ void __launch_bounds__(STREAM_THREADS)
+rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
+                     uint32_t *__restrict__ out, uint32_t d0, uint32_t d1, uint32_t L, uint32_t N,
+                     uint32_t nblk_n, ModQ4 mods) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t nb = bid % nblk_n;
+    const uint32_t gg = bid / nblk_n;          // point group over all primes
+    const uint32_t G = N / 4;
+    const uint32_t l = gg / G, g = gg % G;
+    const ModQ mq = mods.m[l];
+    const uint32_t n = nb * STREAM_THREADS + tid;
+    if (n >= d1) return;
+
+    const uint4 *dcol = db + (uint64_t)gg * d0 * d1 + n;
+    // query vector (m, k) at qv + m*mstride + k*kstride (16-byte units)
+    const uint4 *qv = reinterpret_cast<const uint4 *>(qry + (uint64_t)l * N + 4 * g);
+    const uint64_t kstride = (uint64_t)L * N / 4, mstride = (uint64_t)d0 * kstride;
+    uint64_t acc[MB][4];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[i][s] = 0;
+
+    uint32_t k = 0;
+    for (; k + STREAM_UNROLL <= d0; k += STREAM_UNROLL) {
+        uint4 v[STREAM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < STREAM_UNROLL; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * d1);
+#pragma unroll
+        for (int u = 0; u < STREAM_UNROLL; ++u)
+#pragma unroll
+            for (int i = 0; i < MB; ++i) mad4(acc[i], qv[i * mstride + (k + u) * kstride], v[u]);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[i][s] = lazy_fold(acc[i][s], mq);
+    }
+    if (k < d0) {   // ragged tail: fewer than fifteen rows
+        for (; k < d0; ++k) {
+            const uint4 v = ld_nt(dcol + (uint64_t)k * d1);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) mad4(acc[i], qv[i * mstride + k * kstride], v);
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[i][s] = lazy_fold(acc[i][s], mq);
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        uint4 r;
+        r.x = reduce64(acc[i][0], mq);
+        r.y = reduce64(acc[i][1], mq);
+        r.z = reduce64(acc[i][2], mq);
+        r.w = reduce64(acc[i][3], mq);
+        *reinterpret_cast<uint4 *>(out + (((uint64_t)i * d1 + n) * L + l) * N + 4 * g) = r;
+    }
+}
+
+// ------------------------------------------------------------------ tiled
+// Larger batches: a 256-thread block computes a BM x BN output tile of one
+// point group (four points), thread tile TM x TN x 4 points, staging KC rows
+// of query and DB vectors in LDS per step (the classic tiled GEMM of
+// sec. 5.1.1 with an extra innermost point dimension of four).
+constexpr int TILE_THREADS = 256;
+constexpr int TM = 4, TN = 2;            // per-thread rows x columns
+constexpr int BM = 16 * TM, BN = 16 * TN;
+constexpr int TKC = 30;                   // rows per LDS step (two lazy groups)
+
+__global__ void __launch_bounds__(TILE_THREADS)
+rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
+                    uint32_t *__restrict__ out, uint32_t m_rows, uint32_t d0, uint32_t d1,
+                    uint32_t L, uint32_t N, uint32_t nblk_m, uint32_t nblk_n, ModQ4 mods) {
+    __shared__ uint4 qs[TKC][BM];
+    __shared__ uint4 ds[TKC][BN];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t nb = bid % nblk_n;
+    const uint32_t mb = (bid / nblk_n) % nblk_m;
+    const uint32_t gg = bid / (nblk_n * nblk_m);
+    const uint32_t G = N / 4;
+    const uint32_t l = gg / G, g = gg % G;
+    const ModQ mq = mods.m[l];
+    const uint32_t tm = tid / 16, tn = tid % 16;   // thread's rows tm + 16*i, cols tn + 16*j
+    const uint32_t m0 = mb * BM, n0 = nb * BN;
+
+    const uint4 *dgrp = db + (uint64_t)gg * d0 * d1;
+    uint64_t acc[TM][TN][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[i][j][s] = 0;
+
+    for (uint32_t k0 = 0; k0 < d0; k0 += TKC) {
+        const uint32_t kc = min((uint32_t)TKC, d0 - k0);
+        __syncthreads();
+        for (uint32_t e = tid; e < TKC * BM; e += TILE_THREADS) {
+            uint32_t kk = e / BM, mm = e % BM;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (kk < kc && m0 + mm < m_rows)
+                v = *reinterpret_cast<const uint4 *>(
+                    qry + (((uint64_t)(m0 + mm) * d0 + k0 + kk) * L + l) * N + 4 * g);
+            qs[kk][mm] = v;
+        }
+        for (uint32_t e = tid; e < TKC * BN; e += TILE_THREADS) {
+            uint32_t kk = e / BN, nn = e % BN;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (kk < kc && n0 + nn < d1) v = dgrp[(uint64_t)(k0 + kk) * d1 + n0 + nn];
+            ds[kk][nn] = v;
+        }
+        __syncthreads();
+        // zero-padded rows contribute nothing, so full lazy groups are safe
+#pragma unroll 1
+        for (uint32_t kh = 0; kh < TKC; kh += 15) {
+#pragma unroll 5
+            for (uint32_t kk = kh; kk < kh + 15; ++kk) {
+                uint4 a[TM], b[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) a[i] = qs[kk][tm + 16 * i];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[j] = ds[kk][tn + 16 * j];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) mad4(acc[i][j], a[i], b[j]);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[i][j][s] = lazy_fold(acc[i][j][s], mq);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const uint32_t m = m0 + tm + 16 * i;
+        if (m >= m_rows) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const uint32_t n = n0 + tn + 16 * j;
+            if (n >= d1) continue;
+            uint4 r;
+            r.x = reduce64(acc[i][j][0], mq);
+            r.y = reduce64(acc[i][j][1], mq);
+            r.z = reduce64(acc[i][j][2], mq);
+            r.w = reduce64(acc[i][j][3], mq);
+            *reinterpret_cast<uint4 *>(out + (((uint64_t)m * d1 + n) * L + l) * N + 4 * g) = r;
+        }
+    }
+}
+
+static ModQ4 pack_mods(const pir_db &db) {
+    ModQ4 m{};
+    for (uint32_t l = 0; l < db.p.nprimes; ++l) m.m[l] = db.mod[l];
+    return m;
+}
+
+void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
+                        hipStream_t st) {
+    const auto &p = db.p;
+    const uint32_t m_rows = 2 * B;
+    const uint64_t groups = (uint64_t)p.nprimes * (p.n / 4);
+    const ModQ4 mods = pack_mods(db);
+    const uint4 *dbv = reinterpret_cast<const uint4 *>(db.valu.data);
+    if (m_rows <= 8) {
+        const uint32_t nblk_n = (p.d1 + STREAM_THREADS - 1) / STREAM_THREADS;
+        const uint64_t blocks = groups * nblk_n;
+        if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
+        dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
+#define PIR_STREAM_CASE(MBv)                                                                   \
+    case MBv:                                                                                  \
+        rowsel_stream_kernel<MBv><<<grid, block, 0, st>>>(dbv, q, out, p.d0, p.d1, p.nprimes,  \
+                                                          p.n, nblk_n, mods);                  \
+        break;
+        switch (m_rows) {
+            PIR_STREAM_CASE(2)
+            PIR_STREAM_CASE(4)
+            PIR_STREAM_CASE(6)
+            PIR_STREAM_CASE(8)
+            default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
+        }
+#undef PIR_STREAM_CASE
+    } else {
+        const uint32_t nblk_m = (m_rows + BM - 1) / BM;
+        const uint32_t nblk_n = (p.d1 + BN - 1) / BN;
+        const uint64_t blocks = groups * nblk_m * nblk_n;
+        if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
+        rowsel_tiled_kernel<<<(uint32_t)blocks, TILE_THREADS, 0, st>>>(
+            dbv, q, out, m_rows, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
+    }
+    PIR_LAUNCH_CHECK();
+}
+
+}  // namespace pir
