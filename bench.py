@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-client figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (bitwise_not) "
+                         "so HBM byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,6 +118,13 @@ def main():
 
     pir.lib()
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        src = torch.zeros(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     w, wb = synth.HBM, synth.BATCHED
     log("building DB", w.name)
     t0 = time.time()

@@ -80,6 +80,10 @@ ModQ make_modq(uint32_t q) {
         w = (w << 8) % q;
     }
     m.fold2 = m.r32 >= (1u << 28) ? 1u : 0u;
+    m.qd = (double)q;
+    m.qinv = 1.0 / (double)q;
+    m.c32 = (double)m.r32;
+    m.c47 = (double)(uint32_t)((1ull << 47) % q);
     return m;
 }
 

@@ -58,6 +58,43 @@ __device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t q) 
     return a >= b ? a - b : a + q - b;
 }
 
+// Reduction of an exact integer held in binary64, |x| < 2^52, into [0, q):
+// t = floor(x * (1/q)) is the true quotient or off by one (the product's
+// relative error is below 2^-52 while the quotient is below 2^52/q), the
+// remainder x - t*q is exact in one FMA (both terms are integers below
+// 2^53), and one correction each way brings it into [0, q).
+__device__ __forceinline__ double fp_reduce(double x, const ModQ &m) {
+    const double t = floor(x * m.qinv);
+    double r = fma(-t, m.qd, x);
+    r = r < 0.0 ? r + m.qd : r;
+    r = r >= m.qd ? r - m.qd : r;
+    return r;
+}
+
+// Recombines the seven digit-product classes of one output,
+//   sum_s G_s 2^(8s) mod q,   |G_s| <= 2^27,
+// entirely in exact binary64 arithmetic:
+//   E = G_0 + 2^8 G_1 + 2^16 G_2 + 2^24 G_3       |E| < 2^52 (exact)
+//   H = G_4 + 2^8 G_5 + 2^16 G_6                  |H| < 2^44 (exact)
+//   h = H mod q = 2^15 h1 + h0 (h0, h1 < 2^15)
+//   result = E + h0 (2^32 mod q) + h1 (2^47 mod q)   mod q
+// where each product stays below 2^45, so the sum is exact before reduction.
+__device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const ModQ &m) {
+    double e = (double)g[3];
+    e = fma(e, 256.0, (double)g[2]);
+    e = fma(e, 256.0, (double)g[1]);
+    e = fma(e, 256.0, (double)g[0]);
+    double hh = (double)g[6];
+    hh = fma(hh, 256.0, (double)g[5]);
+    hh = fma(hh, 256.0, (double)g[4]);
+    const double h = fp_reduce(hh, m);
+    const double h1 = floor(h * (1.0 / 32768.0));
+    const double h0 = fma(-h1, 32768.0, h);
+    double t = fma(h0, m.c32, e);
+    t = fma(h1, m.c47, t);
+    return (uint32_t)fp_reduce(t, m);
+}
+
 // Balanced signed base-2^8 digits of x < 2^31: x = sum_i d_i 2^(8i),
 // d_i in [-128, 127] (the top digit of x < 2^30 stays within [0, 64]).
 // Returned packed as four int8 in one 32-bit word, digit i in byte i.
