@@ -117,7 +117,8 @@ pir_status pir_db_params(const pir_db *db, pir_params *out);
 /* Layout flags actually present. */
 uint32_t pir_db_layouts(const pir_db *db);
 
-/* Release a DB (NULL is a no-op).  Synchronises the device first. */
+/* Release a DB (NULL is a no-op).  Synchronises the device first and drops
+ * every cached grouped-call plan. */
 void pir_db_free(pir_db *db);
 
 /* RowSel for B clients against one DB (sec. 2.2, sec. 2.3, sec. 5.1.1):
@@ -131,6 +132,101 @@ void pir_db_free(pir_db *db);
  * the INT8 MFMA kernels for large ones when both layouts exist. */
 pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
                       uint32_t *out_dev, pir_path path, void *hip_stream);
+
+/* One RowSel instance of a grouped call. */
+typedef struct {
+    const pir_db *db;
+    const uint32_t *q_dev;   /* [B][2][D0][L][N] of this instance's DB */
+    uint32_t B;
+    uint32_t *out_dev;       /* [B][2][D1][L][N] */
+} pir_rowsel_item;
+
+/* Many RowSel instances of uneven shape (own DB, own batch) at once (the
+ * counterpart of the paper's per-prime, N-chunked launches under CUDA
+ * Graphs, sec. 5.2.2).  Every item must satisfy the pir_rowsel contract and
+ * live on the current device; outputs of distinct items must not overlap one
+ * another or any query.  Results equal `count` separate pir_rowsel calls bit
+ * for bit.  MFMA path (PIR_PATH_MFMA_I8, or AUTO when every DB holds the MFMA
+ * layout): one query-ingest launch per item, ONE persistent GEMM launch over
+ * the output tiles of all items, one output-transpose launch per item.  VALU
+ * path: the items' RowSel launches back to back.
+ * The first MFMA call for a given list of (db, B) allocates a plan (device
+ * work table and scratch, kept for reuse; up to 8 plans are cached) and must
+ * not be made while the stream is being captured (PIR_EINVAL); later calls
+ * with the same list only enqueue kernels and may be captured into a
+ * hipGraph, with any query/output pointers. */
+pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count,
+                              pir_path path, void *hip_stream);
+
+/* ---------------------------------------------------------------- serving */
+/* A RowSel server over one resident DB with continuous batching.  The DB's
+ * L*N/4 point groups are swept in `chunks` steps; every step runs the INT8
+ * MFMA RowSel of ALL admitted clients on one chunk of points.  A request is
+ * admitted into a free client slot at any step boundary and completes after
+ * one full sweep (`chunks` consecutive steps), so requests that arrive while
+ * others are on the GPU join the running batch instead of waiting for it to
+ * drain.  Every output word depends only on its own client's query and the
+ * DB, so a request's result is bit-identical alone and in any mix.  Needs a
+ * DB with the MFMA layout.  (The paper reports batched throughput only,
+ * Tab. 1; this adds admission, latency and the sweep schedule.) */
+typedef struct pir_server pir_server;
+
+typedef struct {
+    uint32_t max_clients;   /* admission cap (slots), 1..4096; 0 = 256 */
+    uint32_t chunks;        /* sweep steps per pass over the DB, 1..L*N/4; 0 = 16 */
+    uint32_t pipeline;      /* steps kept in flight on the device, 1..4; 0 = 2 */
+    uint32_t reserved;
+    uint64_t hbm_budget;    /* device bytes the server may allocate; 0 = 90% of the
+                               free memory at creation.  Admission capacity is the
+                               number of client slots (64 MiB per client at
+                               N = 4096, L = 2, D0 = 1024) that fit beside the step
+                               staging; creation fails with PIR_ENOMEM if not one fits */
+} pir_server_opts;
+
+typedef struct {
+    uint64_t id;               /* caller's tag, echoed in the completion */
+    const uint32_t *q_dev;     /* [2][D0][L][N] one client's selectors (residues < q_l) */
+    uint32_t *out_dev;         /* [2][D1][L][N]; must not overlap another live request's */
+} pir_request;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;            /* PIR_OK, or this request's own error (others go on) */
+    uint32_t reserved;
+    double t_submit, t_admit, t_done;   /* seconds on pir_clock() */
+} pir_completion;
+
+typedef struct {
+    uint32_t capacity;         /* client slots that fit the budget (<= max_clients) */
+    uint32_t active;           /* clients currently admitted */
+    uint32_t waiting;          /* requests queued for admission */
+    uint32_t inflight;         /* steps on the device */
+    uint64_t steps;            /* steps launched so far */
+    uint64_t admitted;         /* requests admitted so far */
+    uint64_t completed;        /* requests completed so far */
+    uint64_t device_bytes;     /* bytes the server allocated */
+} pir_server_stats;
+
+/* Monotonic clock (seconds) used for the completion time stamps. */
+double pir_clock(void);
+
+pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_server **out);
+
+/* One turn of the serving loop; never blocks on the device.  Queues the
+ * `n_arrivals` requests (stamped t_submit = now; a malformed request completes
+ * at once with PIR_EINVAL), retires finished steps, admits waiting requests
+ * into free slots in arrival order, and launches steps until `pipeline` are
+ * in flight (none while no client is admitted).  Copies up to `cap` finished
+ * requests, oldest first, into `done` and sets *n_done; the rest are kept for
+ * the next call.  The caller keeps each request's buffers alive until its
+ * completion is returned.  Not thread safe: one caller per server. */
+pir_status pir_serve_step(pir_server *srv, const pir_request *arrivals, uint32_t n_arrivals,
+                          pir_completion *done, uint32_t cap, uint32_t *n_done);
+
+pir_status pir_server_get_stats(const pir_server *srv, pir_server_stats *out);
+
+/* Waits for the device, drops pending requests and frees the server. */
+void pir_server_destroy(pir_server *srv);
 
 /* ---------------------------------------------------------------- helpers */
 /* Negacyclic NTT / inverse NTT of `count` contiguous length-n polynomials

@@ -56,6 +56,12 @@ SIGNATURES = {
     "pir_db_layouts": (_u32, [_vp]),
     "pir_db_free": (None, [_vp]),
     "pir_rowsel": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
+    "pir_rowsel_grouped": (_i32, [_vp, _u32, _i32, _vp]),
+    "pir_clock": (ctypes.c_double, []),
+    "pir_server_create": (_i32, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "pir_serve_step": (_i32, [_vp, _vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]),
+    "pir_server_get_stats": (_i32, [_vp, _vp]),
+    "pir_server_destroy": (None, [_vp]),
     "pir_ntt_forward": (_i32, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "pir_ntt_inverse": (_i32, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "pir_last_error": (ctypes.c_char_p, []),
@@ -200,6 +206,108 @@ def pir_rowsel(db: Db, query, out, path: int = PIR_PATH_AUTO, stream=None, B: in
     qp = _ptr(query, "query") if B else 0
     op = _ptr(out, "out") if B else 0
     _check(lib().pir_rowsel(db.handle, qp, B, op, path, _stream(stream)), "pir_rowsel")
+
+
+class pir_rowsel_item(ctypes.Structure):
+    _fields_ = [("db", ctypes.c_void_p), ("q_dev", ctypes.c_void_p), ("B", ctypes.c_uint32),
+                ("out_dev", ctypes.c_void_p)]
+
+
+def pir_rowsel_grouped(items, path: int = PIR_PATH_AUTO, stream=None):
+    """items: list of (Db, query tensor, B, out tensor)."""
+    arr = (pir_rowsel_item * max(1, len(items)))()
+    for i, (db, q, B, out) in enumerate(items):
+        _need_u32(q, "query")
+        _need_u32(out, "out")
+        per_q = 2 * db.d0 * db.nprimes * db.n
+        per_o = 2 * db.d1 * db.nprimes * db.n
+        if q.numel() < B * per_q or out.numel() < B * per_o:
+            raise ValueError(f"item {i}: query/out smaller than B clients")
+        arr[i].db = db.handle
+        arr[i].q_dev = _ptr(q, "query") if B else None
+        arr[i].B = B
+        arr[i].out_dev = _ptr(out, "out") if B else None
+    _check(lib().pir_rowsel_grouped(ctypes.cast(arr, ctypes.c_void_p), len(items), path,
+                                    _stream(stream)), "pir_rowsel_grouped")
+
+
+# ---------------------------------------------------------------- serving
+class pir_server_opts(ctypes.Structure):
+    _fields_ = [("max_clients", _u32), ("chunks", _u32), ("pipeline", _u32), ("reserved", _u32),
+                ("hbm_budget", _u64)]
+
+
+class pir_request(ctypes.Structure):
+    _fields_ = [("id", _u64), ("q_dev", _vp), ("out_dev", _vp)]
+
+
+class pir_completion(ctypes.Structure):
+    _fields_ = [("id", _u64), ("status", ctypes.c_int32), ("reserved", _u32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class pir_server_stats(ctypes.Structure):
+    _fields_ = [("capacity", _u32), ("active", _u32), ("waiting", _u32), ("inflight", _u32),
+                ("steps", _u64), ("admitted", _u64), ("completed", _u64), ("device_bytes", _u64)]
+
+
+def pir_clock() -> float:
+    return lib().pir_clock()
+
+
+class Server:
+    """Owning handle of a pir_server; keeps the DB and every live request's
+    tensors referenced until their completion is returned."""
+
+    def __init__(self, handle, db):
+        self.handle, self.db = handle, db
+        self.live = {}
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.pir_server_destroy(h)
+
+
+def pir_server_create(db: Db, max_clients: int = 0, chunks: int = 0, pipeline: int = 0,
+                      hbm_budget: int = 0) -> Server:
+    o = pir_server_opts(max_clients, chunks, pipeline, 0, hbm_budget)
+    h = _vp()
+    _check(lib().pir_server_create(db.handle, ctypes.byref(o), ctypes.byref(h)), "pir_server_create")
+    return Server(h.value, db)
+
+
+def pir_serve_step(srv: Server, arrivals=(), cap: int = 1024):
+    """arrivals: iterable of (id, query tensor [2][D0][L][N], out tensor [2][D1][L][N]).
+    Returns the list of finished pir_completion records."""
+    arrivals = list(arrivals)
+    arr = (pir_request * max(1, len(arrivals)))()
+    for i, (rid, q, out) in enumerate(arrivals):
+        _need_u32(q, "query")
+        _need_u32(out, "out")
+        arr[i].id, arr[i].q_dev, arr[i].out_dev = rid, _ptr(q, "query"), _ptr(out, "out")
+        srv.live[rid] = (q, out)
+    done = (pir_completion * max(1, cap))()
+    nd = _u32()
+    _check(lib().pir_serve_step(srv.handle, ctypes.cast(arr, _vp), len(arrivals), ctypes.cast(done, _vp), cap,
+                                ctypes.byref(nd)), "pir_serve_step")
+    res = [done[i] for i in range(nd.value)]
+    for c in res:
+        srv.live.pop(c.id, None)
+    return res
+
+
+def pir_server_get_stats(srv: Server) -> pir_server_stats:
+    s = pir_server_stats()
+    _check(lib().pir_server_get_stats(srv.handle, ctypes.byref(s)), "pir_server_get_stats")
+    return s
+
+
+def pir_server_destroy(srv: Server):
+    h, srv.handle = srv.handle, None
+    if h:
+        lib().pir_server_destroy(h)
+    srv.live.clear()
 
 
 def pir_ntt_forward(src, out, n: int, q: int, stream=None):

@@ -229,6 +229,10 @@ void pir_db_free(pir_db *db) {
     if (!db) return;
     (void)hipSetDevice(db->device);
     (void)hipDeviceSynchronize();
+    try {
+        release_group_plans();
+    } catch (...) {
+    }
     dev_free(db->valu.data);
     dev_free(db->mfma.data);
     delete db;
@@ -282,6 +286,55 @@ pir_status pir_rowsel(const pir_db *db, const uint32_t *q, uint32_t B, uint32_t 
     return guarded([&] {
         check_rowsel_args(db, q, B, out);
         rowsel_one(*db, q, B, out, path, as_stream(stream));
+    });
+}
+
+pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count, pir_path path, void *stream) {
+    return guarded([&] {
+        PIR_REQUIRE(count == 0 || items != nullptr, "items is NULL");
+        PIR_REQUIRE(count <= 4096, "at most 4096 items");
+        int dev = 0;
+        PIR_HIP(hipGetDevice(&dev));
+        bool all_mfma = true;
+        for (uint32_t i = 0; i < count; ++i) {
+            check_rowsel_args(items[i].db, items[i].q_dev, items[i].B, items[i].out_dev);
+            PIR_REQUIRE(items[i].db->device == dev, "item %u: DB lives on another device", i);
+            all_mfma = all_mfma && (items[i].db->layouts & PIR_LAYOUT_MFMA);
+        }
+        // outputs must not overlap each other or any query
+        for (uint32_t i = 0; i < count; ++i) {
+            if (!items[i].B) continue;
+            const auto &pi = items[i].db->p;
+            const size_t oi = (size_t)items[i].B * 2 * pi.d1 * items[i].db->slots() * 4;
+            for (uint32_t j = 0; j < count; ++j) {
+                if (!items[j].B) continue;
+                const auto &pj = items[j].db->p;
+                const size_t qj = (size_t)items[j].B * 2 * pj.d0 * items[j].db->slots() * 4;
+                PIR_REQUIRE(!overlaps(items[i].out_dev, oi, items[j].q_dev, qj),
+                            "item %u output overlaps item %u query", i, j);
+                if (j > i) {
+                    const size_t oj = (size_t)items[j].B * 2 * pj.d1 * items[j].db->slots() * 4;
+                    PIR_REQUIRE(!overlaps(items[i].out_dev, oi, items[j].out_dev, oj),
+                                "outputs of items %u and %u overlap", i, j);
+                }
+            }
+        }
+        if (!count) return;
+        hipStream_t st = as_stream(stream);
+        PIR_REQUIRE(path == PIR_PATH_AUTO || path == PIR_PATH_VALU || path == PIR_PATH_MFMA_I8,
+                    "unknown path %d", (int)path);
+        const bool mfma = path == PIR_PATH_MFMA_I8 || (path == PIR_PATH_AUTO && all_mfma);
+        if (mfma) {
+            PIR_REQUIRE(all_mfma, "every DB of an MFMA grouped call needs the MFMA layout");
+            if (env_flag("PIR_VALIDATE"))
+                for (uint32_t i = 0; i < count; ++i)
+                    check_residues(items[i].q_dev, (uint64_t)items[i].B * 2 * items[i].db->p.d0 * items[i].db->slots(),
+                                   items[i].db->p, st);
+            launch_rowsel_mfma_grouped(items, count, st);
+        } else {
+            for (uint32_t i = 0; i < count; ++i)
+                rowsel_one(*items[i].db, items[i].q_dev, items[i].B, items[i].out_dev, PIR_PATH_VALU, st);
+        }
     });
 }
 

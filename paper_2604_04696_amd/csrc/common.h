@@ -161,6 +161,11 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st);
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
+void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st);
+void release_group_plans();
+void check_rowsel_args(const pir_db *db, const uint32_t *q, uint32_t B, const uint32_t *out);
+void rowsel_one(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, pir_path path,
+                hipStream_t st);
 void launch_validate_residues(const uint32_t *x, uint64_t count_per_limb_block, uint32_t n,
                               uint32_t nprimes, const uint32_t *q, uint64_t total,
                               uint32_t *flag, hipStream_t st);

@@ -1,0 +1,38 @@
+// MFMA RowSel jobs: shared by the single, grouped and serving entry points.
+#pragma once
+
+#include "common.h"
+
+namespace pir {
+
+// Per-prime constants of the epilogue.
+struct EpiQ {
+    double qd, qinv, c32, c47;
+    uint32_t q, pad;
+};
+
+// One RowSel instance on the MFMA path.  Its output tiles are numbered
+// [tile0, tile0 + tiles) in the launch's global tile order.
+struct MfmaJob {
+    const int8_t *qd;      // query digit planes [L*N][4][nkc][mstride][64]
+    const int8_t *dbd;     // DB digit planes    [L*N][4][nkc][d1][64]
+    uint32_t *out;         // staging [groups][mp][d1][4] (see out_transpose_kernel)
+    uint32_t m_rows, mp, d1, nkc, L, N;
+    uint32_t mstride;      // rows of a query plane (>= mp)
+    uint32_t g_begin;      // first point group (groups of four points) of this job
+    uint32_t wm;           // waves along m: 4 (128 x 64 tiles) or 2 (64 x 128 tiles)
+    uint32_t nblk_m, nblk_n, groups, tile0, tiles;
+    EpiQ q[PIR_MAX_PRIMES];
+};
+
+
+MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t B, uint32_t tile0,
+                      uint32_t wm);
+uint32_t pick_wm(uint32_t B);
+void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
+                      hipStream_t st);
+void launch_query_digits(const pir_db &db, const uint32_t *q, uint32_t B, int8_t *qd, hipStream_t st);
+void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows, int8_t *qd,
+                              uint32_t mstride, uint32_t row0, hipStream_t st);
+
+}  // namespace pir

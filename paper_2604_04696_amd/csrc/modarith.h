@@ -63,7 +63,8 @@ __device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t q) 
 // relative error is below 2^-52 while the quotient is below 2^52/q), the
 // remainder x - t*q is exact in one FMA (both terms are integers below
 // 2^53), and one correction each way brings it into [0, q).
-__device__ __forceinline__ double fp_reduce(double x, const ModQ &m) {
+template <class M>
+__device__ __forceinline__ double fp_reduce(double x, const M &m) {
     const double t = floor(x * m.qinv);
     double r = fma(-t, m.qd, x);
     r = r < 0.0 ? r + m.qd : r;
@@ -79,7 +80,9 @@ __device__ __forceinline__ double fp_reduce(double x, const ModQ &m) {
 //   h = H mod q = 2^15 h1 + h0 (h0, h1 < 2^15)
 //   result = E + h0 (2^32 mod q) + h1 (2^47 mod q)   mod q
 // where each product stays below 2^45, so the sum is exact before reduction.
-__device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const ModQ &m) {
+// (M is any struct with qd, qinv, c32, c47.)
+template <class M>
+__device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const M &m) {
     double e = (double)g[3];
     e = fma(e, 256.0, (double)g[2]);
     e = fma(e, 256.0, (double)g[1]);

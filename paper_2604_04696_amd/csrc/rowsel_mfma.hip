@@ -19,11 +19,15 @@
 //   query digits [L*N][4][Kp/64][Mp][64] int8   built per call (ingest kernel)
 // with Kp = D0 rounded up to 64 and Mp = 2B rounded up to 32, zero padded.
 #include <algorithm>
+#include <list>
+#include <mutex>
+#include <vector>
 #include <cstdio>
 #include <cstdlib>
 
 #include "common.h"
 #include "modarith.h"
+#include "mfma.h"
 
 namespace pir {
 
@@ -47,7 +51,7 @@ __global__ void __launch_bounds__(256)
 digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k,
                     int8_t *__restrict__ dst, uint32_t R, uint32_t r_valid, uint32_t P,
                     uint32_t kp, uint32_t klo, uint32_t khi, uint32_t kvalid, uint32_t kblk0,
-                    uint32_t nkblk) {
+                    uint32_t nkblk, uint32_t RS, uint32_t row0) {
     __shared__ uint32_t tile[64][65];
     const uint32_t tid = threadIdx.x;
     uint64_t b = blockIdx.x;
@@ -84,7 +88,7 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
                 x |= ((tile[kq * 16 + i4 * 4 + i][pp] >> (8 * d)) & 0xFFu) << (8 * i);
             w[i4] = x;
         }
-        int8_t *o = dst + ((((uint64_t)(p0 + pp) * 4 + d) * (kp / 64) + kc / 64) * R + r) * 64 + kc % 64;
+        int8_t *o = dst + ((((uint64_t)(p0 + pp) * 4 + d) * (kp / 64) + kc / 64) * RS + row0 + r) * 64 + kc % 64;
         if (inside) {
             *reinterpret_cast<uint4 *>(o) = make_uint4(w[0], w[1], w[2], w[3]);
         } else {
@@ -98,7 +102,9 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
 
 static void launch_digit_planes(const uint32_t *src, uint64_t s_r, uint64_t s_k, int8_t *dst,
                                 uint32_t R, uint32_t r_valid, uint32_t P, uint32_t kp,
-                                uint32_t klo, uint32_t khi, uint32_t kvalid, hipStream_t st) {
+                                uint32_t klo, uint32_t khi, uint32_t kvalid, hipStream_t st,
+                                uint32_t RS = 0, uint32_t row0 = 0) {
+    if (!RS) RS = R;
     if (klo >= khi || R == 0) return;
     // blocks cover [klo, khi); when khi = D0 the last block also zero-fills
     // the padding up to Kp (Kp is D0 rounded up to 64)
@@ -107,7 +113,7 @@ static void launch_digit_planes(const uint32_t *src, uint64_t s_r, uint64_t s_k,
     const uint64_t blocks = (uint64_t)((P + 63) / 64) * nkb * R;
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "digit-plane launch too large");
     digit_planes_kernel<<<(uint32_t)blocks, 256, 0, st>>>(src, s_r, s_k, dst, R, r_valid, P, kp, klo,
-                                                          khi, kvalid, kb0, nkb);
+                                                          khi, kvalid, kb0, nkb, RS, row0);
     PIR_LAUNCH_CHECK();
 }
 
@@ -130,13 +136,24 @@ size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B) {
 // ------------------------------------------------------------- the GEMM
 constexpr int KCH = 64;             // k bytes per pipeline step (two MFMA k-steps of 32)
 constexpr uint32_t KSUPER = 2048;   // rows per int32 accumulation (bound above)
+constexpr int NWAVE = 8;            // waves per block
+constexpr int ROWS = 192;           // BM + BN of every tile shape (128 x 64 or 64 x 128)
+constexpr int STAGE_BYTES = 4 * ROWS * KCH;            // 48 KiB: A and B digit planes of one step
+constexpr int NSTAGE = 3;                              // LDS pipeline depth
+constexpr int LPW = (4 * ROWS / 16) / NWAVE;           // 16-row, 1 KiB load instructions per wave per step
+static_assert(LPW * NWAVE * 16 == 4 * ROWS, "loads must divide among the waves");
 
 // LDS rows are 64 bytes (four 16-byte chunks).  Chunk c of row r is stored at
-// position c ^ swz(r).  Reading one chunk index across consecutive rows then
-// hits distinct 16-byte bank groups both for 8 rows in 128 bytes of banks and
-// for 16 rows in 256 bytes of banks (rows r, r+4, r+8, r+12 get four
-// different positions).
+// position c ^ swz(r), which spreads the rows a wavefront reads at one chunk
+// index over different bank groups.
 __device__ __forceinline__ uint32_t swz(uint32_t r) { return ((r >> 1) ^ (r >> 3)) & 3u; }
+
+// Waits until at most N vector-memory operations of this wave are
+// outstanding (they complete in issue order for this count).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 
 // Workgroup barrier without the memory fences of __syncthreads(): those make
 // the compiler wait for every outstanding global load, which would drain the
@@ -146,161 +163,256 @@ __device__ __forceinline__ uint32_t swz(uint32_t r) { return ((r >> 1) ^ (r >> 3
 // reaches the barrier after which that buffer is refilled.
 __device__ __forceinline__ void block_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// Waits until at most N vector-memory loads of this wave are outstanding
-// (loads complete in issue order for this count).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
+// Wave-uniform description of one output tile.
+struct Tile {
+    const int8_t *qd, *dbd;
+    uint32_t *out;
+    uint32_t m_rows, mp, mstride, d1, nkc, L, N, bm, bn, wn, l, g, m0, n0, job, gl;
+};
 
-// One block = a group of four consecutive points of one prime and a BM x BN
-// output tile; WM x WN waves, each owning a 32 x 32 sub-tile with seven int32
-// class accumulators (sixteen digit products per k-step of 32).
-//
-// Operands move global -> LDS with global_load_lds_dwordx4 (no register
-// staging) into STAGES buffers: while the waves run the MFMAs of step t, the
-// loads of steps t+1 .. t+STAGES-1 are in flight.  Steps run over (point, k chunk) in one
-// sequence, so the pipeline does not drain between the four points.  The
-// four residues of each (m, n) stay in registers and leave as one 16-byte
-// vector into the boundary layout [B][2][D1][L][N].
-template <int WM, int WN, int STAGES>
-__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2, 2)))
-rowsel_mfma_kernel(const int8_t *__restrict__ dbd, const int8_t *__restrict__ qd,
-                   uint32_t *__restrict__ out, uint32_t m_rows, uint32_t mp, uint32_t d1,
-                   uint32_t kp, uint32_t L, uint32_t N, uint32_t nblk_m, uint32_t nblk_n,
-                   ModQ4m mods) {
-    constexpr int BM = 32 * WM, BN = 32 * WN, NW = WM * WN;
-    constexpr int A_BYTES = 4 * BM * KCH, B_BYTES = 4 * BN * KCH;
-    constexpr int BUF = A_BYTES + B_BYTES;
-    constexpr int A_INST = 4 * BM / 16, B_INST = 4 * BN / 16;   // 1 KiB = 16 rows per instruction
-    constexpr int INST = A_INST + B_INST;
-    static_assert(INST % NW == 0, "load instructions must divide among the waves");
-    constexpr int LPW = INST / NW;   // load instructions per wave per step
-    __shared__ __attribute__((aligned(1024))) int8_t lds[STAGES * BUF];
-
-    const uint32_t tid = threadIdx.x;
-    // Block order: eight consecutive point groups (32 points = one 128-byte
-    // output line per (m, n)) run side by side for each output tile, so the
-    // 16-byte stores of those groups meet in one XCD's L2 and leave as whole
-    // lines; the tiles of one octet follow each other closely, so its query
-    // planes are re-read from L2.
-    const uint32_t groups = gridDim.x / (nblk_m * nblk_n);
-    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t tiles = nblk_m * nblk_n, per_oct = 8 * tiles, full = groups / 8;
+// Global tile index -> tile.  Within a job, eight consecutive point groups
+// (32 points: the points one output line holds per (m, n)) are numbered
+// together for each (m, n) block, and the blocks of one octet follow each
+// other, so concurrently processed tiles share query planes and output lines.
+__device__ __forceinline__ Tile decode_tile(uint32_t T, const MfmaJob &J, uint32_t j) {
+    const uint32_t loc = T - J.tile0;
+    const uint32_t tiles = J.nblk_m * J.nblk_n, per_oct = 8 * tiles, full = J.groups / 8;
     uint32_t gg, tile;
-    if (bid < full * per_oct) {
-        gg = (bid / per_oct) * 8 + bid % 8;
-        tile = (bid % per_oct) / 8;
+    if (loc < full * per_oct) {
+        gg = (loc / per_oct) * 8 + loc % 8;
+        tile = (loc % per_oct) / 8;
     } else {
-        const uint32_t rem = bid - full * per_oct, w = groups - full * 8;
+        const uint32_t rem = loc - full * per_oct, w = J.groups - full * 8;
         gg = full * 8 + rem % w;
         tile = rem / w;
     }
-    const uint32_t nb = tile % nblk_n, mb = tile / nblk_n;
-    const uint32_t G = N / 4;
-    const uint32_t l = gg / G, g = gg % G;
-    const ModQ mq = mods.m[l];
-    const uint32_t wave = tid / 64, lane = tid % 64;
-    const uint32_t wm = wave / WN, wn = wave % WN;
-    const uint32_t m0 = mb * BM, n0 = nb * BN;
-    const bool wave_active = m0 + wm * 32 < mp && n0 + wn * 32 < d1;
-    const uint32_t nkc = kp / KCH;
-    const uint32_t T = 4 * nkc;              // pipeline steps: 4 points x k chunks
+    Tile t;
+    t.gl = gg;            // group index inside the job (staging row block)
+    gg += J.g_begin;
+    t.qd = J.qd;
+    t.dbd = J.dbd;
+    t.out = J.out;
+    t.m_rows = J.m_rows;
+    t.mp = J.mp;
+    t.mstride = J.mstride;
+    t.d1 = J.d1;
+    t.nkc = J.nkc;
+    t.L = J.L;
+    t.N = J.N;
+    t.bm = 32 * J.wm;
+    t.bn = ROWS - t.bm;
+    t.wn = NWAVE / J.wm;
+    const uint32_t G = J.N / 4;
+    t.l = gg / G;
+    t.g = gg % G;
+    t.m0 = (tile / J.nblk_n) * t.bm;
+    t.n0 = (tile % J.nblk_n) * t.bn;
+    t.job = j;
+    return t;
+}
 
-    // Per-lane byte offsets of this wave's load instructions inside their
-    // operand plane (fixed for the whole block), and the wave-uniform parts
-    // (plane, LDS destination) computed per step with scalar arithmetic.
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
-    const uint32_t lrow = lane / 4, lchunk = lane % 4;
-    uint32_t loff[LPW];
-#pragma unroll
-    for (int i = 0; i < LPW; ++i) {
-        const uint32_t ii = wv + i * NW;
-        if (ii < (uint32_t)A_INST) {
-            const uint32_t r = (ii % (BM / 16)) * 16 + lrow;
-            loff[i] = min(m0 + r, mp - 1) * KCH + 16 * (lchunk ^ swz(r));
-        } else {
-            const uint32_t jj = ii - A_INST;
-            const uint32_t r = (jj % (BN / 16)) * 16 + lrow;
-            loff[i] = min(n0 + r, d1 - 1) * KCH + 16 * (lchunk ^ swz(r));
-        }
-    }
-    const uint64_t a_plane = (uint64_t)mp * KCH, b_plane = (uint64_t)d1 * KCH;   // bytes per (p, d, kc)
+// Load side of the pipeline for one wave and tile shape BM x BN: which
+// operand, digit plane and 16-row block each of the wave's LPW load
+// instructions covers is fixed by (wave, instruction); everything that
+// depends on the tile is computed when a tile starts, and a step costs a few
+// 64-bit scalar adds per load.  Byte offset of (point s, digit d, chunk kc,
+// row r) in a plane set: ((s*4 + d)*nkc + kc)*plane + r*64, plane = rows*64.
+template <int BM>
+struct LoadCursor {
+    static constexpr int BN = ROWS - BM;
+    static constexpr int A_INST = 4 * BM / 16;   // query instructions (16 rows each)
+    const int8_t *qbase, *dbase;                 // planes of the tile's first point
+    uint64_t qstep, dstep, qplane, dplane;       // current (s, kc) offset, plane bytes
+    uint64_t doff[LPW];                          // d * nkc * plane per instruction
+    uint32_t loff[LPW];                          // per lane: clamped row * 64 + swizzled chunk
+    uint32_t kc, s, nkc;
 
-    auto issue = [&](uint32_t t) {
-        const uint32_t s = t / nkc, kc = t % nkc;
-        const uint64_t p = (uint64_t)l * N + 4 * g + s;
-        int8_t *buf = lds + (t % STAGES) * BUF;
+    static __device__ __forceinline__ bool is_q(int i, uint32_t wv) { return wv + i * NWAVE < (uint32_t)A_INST; }
+
+    __device__ __forceinline__ void start(const Tile &t, uint32_t wv, uint32_t lane) {
+        const uint64_t p0 = (uint64_t)t.l * t.N + 4 * t.g;
+        qplane = (uint64_t)t.mstride * KCH;
+        dplane = (uint64_t)t.d1 * KCH;
+        qbase = t.qd + p0 * 4 * t.nkc * qplane;
+        dbase = t.dbd + p0 * 4 * t.nkc * dplane;
+        qstep = dstep = 0;
+        kc = s = 0;
+        nkc = t.nkc;
+        const uint32_t lrow = lane / 4, lchunk = lane % 4;
 #pragma unroll
         for (int i = 0; i < LPW; ++i) {
-            const uint32_t ii = wv + i * NW;
-            const int8_t *plane;
-            int8_t *dst;
-            if (ii < (uint32_t)A_INST) {
-                const uint32_t d = ii / (BM / 16);
-                plane = qd + ((p * 4 + d) * nkc + kc) * a_plane;
-                dst = buf + d * BM * KCH + (ii % (BM / 16)) * 1024;
-            } else {
-                const uint32_t jj = ii - A_INST;
-                const uint32_t d = jj / (BN / 16);
-                plane = dbd + ((p * 4 + d) * nkc + kc) * b_plane;
-                dst = buf + A_BYTES + d * BN * KCH + (jj % (BN / 16)) * 1024;
-            }
+            const uint32_t ii = wv + i * NWAVE;
+            const bool q = ii < (uint32_t)A_INST;
+            const uint32_t jj = q ? ii : ii - A_INST, rbn = q ? BM / 16 : BN / 16;
+            const uint32_t d = jj / rbn, rb = jj % rbn, r = rb * 16 + lrow;
+            doff[i] = (uint64_t)d * t.nkc * (q ? qplane : dplane);
+            loff[i] = q ? min(t.m0 + r, t.mp - 1) * KCH : min(t.n0 + r, t.d1 - 1) * KCH;
+            loff[i] += 16 * (lchunk ^ swz(r));
+        }
+    }
+
+    // LDS destination of instruction i inside a stage
+    static __device__ __forceinline__ uint32_t lds_off(int i, uint32_t wv) {
+        const uint32_t ii = wv + i * NWAVE;
+        if (ii < (uint32_t)A_INST) return (ii / (BM / 16)) * BM * KCH + (ii % (BM / 16)) * 1024;
+        const uint32_t jj = ii - A_INST;
+        return 4 * BM * KCH + (jj / (BN / 16)) * BN * KCH + (jj % (BN / 16)) * 1024;
+    }
+
+    // Issues this wave's loads of the current step into `stage`; returns
+    // true when the tile's last step has been issued.
+    __device__ __forceinline__ bool issue(int8_t *stage, uint32_t wv) {
+#pragma unroll
+        for (int i = 0; i < LPW; ++i) {
             // (a named pointer: an arithmetic expression as the builtin's
             // argument stops the host pass from emitting the kernel stub)
-            const int8_t *src = plane + loff[i];
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+            const int8_t *src = (is_q(i, wv) ? qbase + qstep : dbase + dstep) + doff[i] + loff[i];
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(stage + lds_off(i, wv)),
+                                             16, 0, 0);
+        }
+        qstep += qplane;
+        dstep += dplane;
+        if (++kc == nkc) {
+            kc = 0;
+            qstep += 3ull * nkc * qplane;
+            dstep += 3ull * nkc * dplane;
+            if (++s == 4) return true;
+        }
+        return false;
+    }
+};
+
+// Persistent block: processes global tiles T = (i*8 + x)*per_xcd + y for
+// i = 0, 1, ..., where x is the block's XCD (blocks are dealt to the XCDs
+// round-robin) and y its index there; at any moment the tiles in flight on
+// one XCD are consecutive in the tile order.  Each tile runs 4 points x nkc
+// steps; the LDS pipeline runs over the concatenated steps of all the
+// block's tiles without draining at tile boundaries.
+//
+// Per step a wave owns a 32 x 32 sub-tile and issues 2 k-steps x 16 MFMAs
+// (four query digits x four DB digits) into seven int32 class accumulators.
+//
+// A single instance travels by value in `one` (ONE = true); a grouped launch
+// passes a device array of jobs sorted by tile0.
+template <bool ONE, int BM>
+__global__ void __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
+rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint32_t njobs,
+                       uint32_t total_tiles) {
+    __shared__ __attribute__((aligned(1024))) int8_t lds[NSTAGE * STAGE_BYTES];
+    auto decode = [&](uint32_t T) {
+        uint32_t j = 0;
+        if (!ONE)
+            while (j + 1 < njobs && T >= jobs[j + 1].tile0) ++j;
+        return decode_tile(T, ONE ? one : jobs[j], j);
+    };
+
+    const uint32_t tid = threadIdx.x, lane = tid % 64;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid / 64);
+    const uint32_t per_xcd = gridDim.x / 8;
+    const uint32_t xcd = blockIdx.x % 8, yi = blockIdx.x / 8;
+    auto tile_index = [&](uint32_t i) { return (i * 8 + xcd) * per_xcd + yi; };
+    const uint32_t half = lane / 32;
+
+    // ---- load cursor
+    uint32_t li = 0;
+    bool l_done = tile_index(0) >= total_tiles;
+    Tile lt{};
+    LoadCursor<BM> lc;
+    if (!l_done) {
+        lt = decode(tile_index(0));
+        lc.start(lt, wv, lane);
+    }
+    uint32_t lbuf = 0;   // stage of the next issue
+    auto issue_next = [&]() {
+        const bool tile_end = lc.issue(lds + lbuf * STAGE_BYTES, wv);
+        lbuf = lbuf + 1 == NSTAGE ? 0 : lbuf + 1;
+        if (tile_end) {
+            ++li;
+            l_done = tile_index(li) >= total_tiles;
+            if (!l_done) {
+                lt = decode(tile_index(li));
+                lc.start(lt, wv, lane);
+            }
         }
     };
 
-    uint32_t res[4][16];
+    // ---- compute cursor (per-tile values refreshed when a tile starts)
+    uint32_t ci = 0, s = 0, kc = 0, cbuf = 0;
+    bool c_done = l_done;
+    Tile ct = lt;
+    uint32_t wmi = 0, wni = 0, abase = 0, bbase = 0, a_stride = 0, b_stride = 0;
+    bool active = false;
+    auto start_compute = [&]() {
+        wmi = wv / ct.wn;
+        wni = wv % ct.wn;
+        active = ct.m0 + wmi * 32 < ct.mp && ct.n0 + wni * 32 < ct.d1;
+        a_stride = ct.bm * KCH;
+        b_stride = ct.bn * KCH;
+        abase = (wmi * 32 + lane % 32) * KCH;
+        bbase = 4 * a_stride + (wni * 32 + lane % 32) * KCH;
+    };
+    if (!c_done) start_compute();
+    uint32_t achunk[2], bchunk[2];   // swizzled 16-byte chunk of each k-step
+    auto chunks = [&]() {
+        const uint32_t ar = wmi * 32 + lane % 32, br = wni * 32 + lane % 32;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            achunk[ks] = 16 * ((2 * ks + half) ^ swz(ar));
+            bchunk[ks] = 16 * ((2 * ks + half) ^ swz(br));
+        }
+    };
+    chunks();
+
     i32x16 acc[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
+    uint32_t res[4][16];
 
-    // fragment byte offsets inside a buffer, per k-step (digit planes follow
-    // at fixed strides)
-    const uint32_t ar = wm * 32 + lane % 32, br = wn * 32 + lane % 32;   // fragment rows
-    const uint32_t half = lane / 32;
-    uint32_t aoff[2], boff[2];
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        aoff[ks] = ar * KCH + 16 * ((2 * ks + half) ^ swz(ar));
-        boff[ks] = A_BYTES + br * KCH + 16 * ((2 * ks + half) ^ swz(br));
+    uint32_t outstanding = 0;   // steps issued beyond the one being computed
+    for (int k = 0; k < NSTAGE - 1 && !l_done; ++k) {
+        issue_next();
+        ++outstanding;
     }
 
-    for (uint32_t t = 0; t + 1 < STAGES && t < T; ++t) issue(t);
-    for (uint32_t t = 0; t < T; ++t) {
-        // this wave's loads of step t are done once only the later steps'
-        // (up to STAGES-2 of them) are outstanding; the barrier then makes
-        // every wave's part visible and frees the buffer of step t-1
-        if (t + STAGES - 2 < T) wait_vmcnt<(STAGES - 2) * LPW>();
+    bool after_store = false;
+    while (!c_done) {
+        // the loads of the current step are done once at most the NSTAGE-2
+        // later steps' loads are outstanding (after output stores, or near
+        // the end, wait for everything)
+        --outstanding;
+        if (!after_store && outstanding == NSTAGE - 2) wait_vmcnt<(NSTAGE - 2) * LPW>();
         else wait_vmcnt<0>();
+        after_store = false;
         block_barrier();
-        if (t + STAGES - 1 < T) issue(t + STAGES - 1);
-        const int8_t *buf = lds + (t % STAGES) * BUF;
-        if (wave_active) {
+        if (!l_done) {
+            issue_next();
+            ++outstanding;
+        }
+
+        if (active) {
+            const int8_t *buf = lds + cbuf * STAGE_BYTES;
+            const int8_t *abuf = buf + abase, *bbuf = buf + bbase;
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 i32x4 a[4];
 #pragma unroll
                 for (int d = 0; d < 4; ++d)
-                    a[d] = *reinterpret_cast<const i32x4 *>(buf + aoff[ks] + d * BM * KCH);
-                // one DB digit at a time: four MFMAs into four different classes
+                    a[d] = *reinterpret_cast<const i32x4 *>(abuf + d * a_stride + achunk[ks]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const i32x4 b = *reinterpret_cast<const i32x4 *>(buf + boff[ks] + j * BN * KCH);
+                    const i32x4 b = *reinterpret_cast<const i32x4 *>(bbuf + j * b_stride + bchunk[ks]);
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
                         acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b, acc[i + j], 0, 0, 0);
                 }
             }
         }
-        const uint32_t s = t / nkc, kc = t % nkc;
-        const bool last = kc + 1 == nkc;
-        const bool flush = last || ((kc + 1) * KCH) % KSUPER == 0;
-        if (flush) {
-            // recombine the seven classes: sum_s G_s * 2^(8s) mod q
+        cbuf = cbuf + 1 == NSTAGE ? 0 : cbuf + 1;
+        const bool last = kc + 1 == ct.nkc;
+        if (last || ((kc + 1) * KCH) % KSUPER == 0) {
+            // recombine the seven classes of this point: sum_s G_s 2^(8s) mod q
+            const EpiQ mq = ONE ? one.q[ct.l] : jobs[ct.job].q[ct.l];
+            const bool first = kc + 1 <= KSUPER / KCH;
             uint32_t part[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -309,7 +421,6 @@ rowsel_mfma_kernel(const int8_t *__restrict__ dbd, const int8_t *__restrict__ qd
                 for (int c = 0; c < 7; ++c) gr[c] = acc[c][r];
                 part[r] = combine_classes(gr, mq);
             }
-            const bool first = kc + 1 <= KSUPER / KCH;
 #pragma unroll
             for (int ss = 0; ss < 4; ++ss) {
                 if ((uint32_t)ss != s) continue;
@@ -319,88 +430,301 @@ rowsel_mfma_kernel(const int8_t *__restrict__ dbd, const int8_t *__restrict__ qd
 #pragma unroll
             for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
         }
-    }
-
-    if (!wave_active) return;
-    // accumulator element r of a lane: row 8*(r/4) + 4*(lane/32) + r%4, column lane%32
-    const uint32_t n = n0 + wn * 32 + lane % 32;
-    if (n >= d1) return;
+        if (++kc == ct.nkc) {
+            kc = 0;
+            if (++s == 4) {
+                // the tile's four points are done: one 16-byte vector per
+                // (m, n) into the staging layout [group][mp][d1][4], where the
+                // 32 lanes of a row write 512 contiguous bytes.  Accumulator
+                // element r of a lane is row 8*(r/4) + 4*(lane/32) + r%4,
+                // column lane%32 of the wave's 32 x 32 sub-tile.
+                const uint32_t n = ct.n0 + wni * 32 + lane % 32;
+                if (active && n < ct.d1) {
+                    uint32_t *grp = ct.out + (uint64_t)ct.gl * ct.mp * ct.d1 * 4;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const uint32_t m = m0 + wm * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-        if (m < m_rows)
-            *reinterpret_cast<uint4 *>(out + (((uint64_t)m * d1 + n) * L + l) * N + 4 * g) =
-                make_uint4(res[0][r], res[1][r], res[2][r], res[3][r]);
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t m = ct.m0 + wmi * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                        *reinterpret_cast<uint4 *>(grp + ((uint64_t)m * ct.d1 + n) * 4) =
+                            make_uint4(res[0][r], res[1][r], res[2][r], res[3][r]);
+                    }
+                }
+                after_store = true;
+                s = 0;
+                ++ci;
+                c_done = tile_index(ci) >= total_tiles;
+                if (!c_done) {
+                    ct = decode(tile_index(ci));
+                    start_compute();
+                    chunks();
+                }
+            }
+        }
     }
 }
 
-template <int WM, int WN, int STAGES>
-static void launch_mfma_tile(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t m_rows,
-                             uint32_t mp, const ModQ4m &mods, hipStream_t st) {
-    const auto &p = db.p;
-    const uint64_t groups = (uint64_t)p.nprimes * (p.n / 4);
-    const uint32_t nblk_m = (mp + 32 * WM - 1) / (32 * WM);
-    const uint32_t nblk_n = (p.d1 + 32 * WN - 1) / (32 * WN);
-    const uint64_t blocks = groups * nblk_m * nblk_n;
-    if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
-    rowsel_mfma_kernel<WM, WN, STAGES><<<(uint32_t)blocks, 64 * WM * WN, 0, st>>>(
-        db.mfma.data, qd, out, m_rows, mp, p.d1, db.mfma.kp, p.nprimes, p.n, nblk_m, nblk_n, mods);
+// Output transpose: staging [G_all][mp][d1][4] (G_all = L*N/4 point groups)
+// -> boundary layout [B][2][d1][L][N].  A block takes one row m, 32 columns
+// and 32 consecutive groups (128 points): it reads 32 runs of 512 bytes
+// (one per group) and writes 32 runs of 512 bytes (one per column), so both
+// sides move whole cache lines (the paper's output transposition of
+// sec. 5.2.2, here a separate coalesced pass instead of 16-byte scatter).
+__global__ void __launch_bounds__(256)
+out_transpose_kernel(const uint4 *__restrict__ stage, uint4 *__restrict__ out, uint32_t m_rows,
+                     uint32_t mp, uint32_t d1, uint32_t gall, uint32_t nblk_n, uint32_t nblk_g) {
+    __shared__ uint4 tile[32][33];   // [column][group]
+    const uint32_t tid = threadIdx.x;
+    uint32_t b = blockIdx.x;
+    const uint32_t gb = b % nblk_g;
+    b /= nblk_g;
+    const uint32_t nb = b % nblk_n;
+    const uint32_t m = b / nblk_n;
+    const uint32_t g0 = gb * 32, n0 = nb * 32;
+    for (uint32_t e = tid; e < 1024; e += 256) {
+        const uint32_t gi = e / 32, ni = e % 32;
+        if (g0 + gi < gall && n0 + ni < d1)
+            tile[ni][gi] = stage[((uint64_t)(g0 + gi) * mp + m) * d1 + n0 + ni];
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < 1024; e += 256) {
+        const uint32_t ni = e / 32, gi = e % 32;
+        if (g0 + gi < gall && n0 + ni < d1) out[((uint64_t)m * d1 + n0 + ni) * gall + g0 + gi] = tile[ni][gi];
+    }
+}
+
+void launch_out_transpose(const uint32_t *stage, uint32_t *out, uint32_t m_rows, uint32_t mp, uint32_t d1,
+                          uint32_t slots, hipStream_t st) {
+    const uint32_t gall = slots / 4;
+    const uint32_t nblk_n = (d1 + 31) / 32, nblk_g = (gall + 31) / 32;
+    const uint64_t blocks = (uint64_t)m_rows * nblk_n * nblk_g;
+    if (!blocks) return;
+    if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "transpose launch too large");
+    out_transpose_kernel<<<(uint32_t)blocks, 256, 0, st>>>(reinterpret_cast<const uint4 *>(stage),
+                                                           reinterpret_cast<uint4 *>(out), m_rows, mp, d1,
+                                                           gall, nblk_n, nblk_g);
     PIR_LAUNCH_CHECK();
 }
 
-// Tile variants: (waves along m, waves along n, pipeline stages).
-struct MfmaTile {
-    int wm, wn, stages;
-};
-
-static const MfmaTile kTiles[] = {
-    {4, 2, 3}, {2, 4, 3}, {1, 8, 2}, {2, 2, 2}, {4, 1, 2}, {1, 4, 2}, {2, 2, 3},
-};
-
-static void launch_tile(const MfmaTile &t, const pir_db &db, const int8_t *qd, uint32_t *out,
-                        uint32_t m_rows, uint32_t mp, const ModQ4m &mods, hipStream_t st) {
-#define PIR_TILE(a, b, c)                                                      \
-    if (t.wm == a && t.wn == b && t.stages == c)                               \
-        return launch_mfma_tile<a, b, c>(db, qd, out, m_rows, mp, mods, st);
-    PIR_TILE(4, 2, 3)
-    PIR_TILE(2, 4, 3)
-    PIR_TILE(1, 8, 2)
-    PIR_TILE(2, 2, 2)
-    PIR_TILE(4, 1, 2)
-    PIR_TILE(1, 4, 2)
-    PIR_TILE(2, 2, 3)
-#undef PIR_TILE
-    PIR_FAIL(PIR_EINVAL, "unknown MFMA tile %d,%d,%d", t.wm, t.wn, t.stages);
+static int cu_count() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0;
+        PIR_HIP(hipGetDevice(&dev));
+        PIR_HIP(hipDeviceGetAttribute(&cached, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    return cached;
 }
 
-static MfmaTile pick_tile(uint32_t mp) {
-    if (const char *e = std::getenv("PIR_MFMA_TILE")) {   // explicit choice (tuning runs)
-        MfmaTile t{};
-        if (std::sscanf(e, "%d,%d,%d", &t.wm, &t.wn, &t.stages) == 3) return t;
+// Fills a job for one instance; `tile0` is its first global tile index.
+MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t B, uint32_t tile0,
+                      uint32_t wm) {
+    const auto &p = db.p;
+    MfmaJob j{};
+    j.qd = qd;
+    j.dbd = db.mfma.data;
+    j.out = out;
+    j.m_rows = 2 * B;
+    j.mp = (j.m_rows + 31) / 32 * 32;
+    j.mstride = j.mp;
+    j.g_begin = 0;
+    j.d1 = p.d1;
+    j.nkc = db.mfma.kp / KCH;
+    j.L = p.nprimes;
+    j.N = p.n;
+    j.wm = wm;
+    j.groups = p.nprimes * (p.n / 4);
+    j.nblk_m = (j.mp + 32 * wm - 1) / (32 * wm);
+    j.nblk_n = (p.d1 + 32 * (NWAVE / wm) - 1) / (32 * (NWAVE / wm));
+    j.tile0 = tile0;
+    j.tiles = j.groups * j.nblk_m * j.nblk_n;
+    for (uint32_t l = 0; l < p.nprimes; ++l) {
+        const ModQ &m = db.mod[l];
+        j.q[l] = EpiQ{m.qd, m.qinv, m.c32, m.c47, m.q, 0};
     }
-    if (mp >= 128) return {4, 2, 3};
-    if (mp >= 64) return {2, 4, 3};
-    return {1, 8, 2};
+    return j;
+}
+
+// Tile shape: 128 x 64 when the batch fills 128 rows, else 64 x 128.
+uint32_t pick_wm(uint32_t B) {
+    if (const char *e = std::getenv("PIR_MFMA_WM")) {   // explicit choice (tuning runs)
+        const int v = std::atoi(e);
+        if (v == 2 || v == 4) return (uint32_t)v;
+    }
+    return 2 * B > 64 ? 4u : 2u;
+}
+
+// One persistent block per CU.  Either `one` (jobs_dev == NULL, njobs == 1)
+// or a device array of njobs jobs.
+void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
+                      hipStream_t st) {
+    if (!total_tiles) return;
+    const uint32_t grid = 8 * (uint32_t)std::max(1, cu_count() / 8);
+    // every job of one launch shares the tile shape of `one`
+    if (one.wm == 4) {
+        if (jobs_dev) rowsel_mfma_persistent<false, 128><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
+        else rowsel_mfma_persistent<true, 128><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+    } else {
+        if (jobs_dev) rowsel_mfma_persistent<false, 64><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
+        else rowsel_mfma_persistent<true, 64><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+    }
+    PIR_LAUNCH_CHECK();
+}
+
+void launch_query_digits(const pir_db &db, const uint32_t *q, uint32_t B, int8_t *qd, hipStream_t st) {
+    const auto &p = db.p;
+    const uint32_t P = p.n * p.nprimes;
+    const uint32_t mp = (2 * B + 31) / 32 * 32;
+    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, mp, 2 * B, P, db.mfma.kp, 0, p.d0, p.d0, st);
+}
+
+void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows, int8_t *qd,
+                              uint32_t mstride, uint32_t row0, hipStream_t st) {
+    const auto &p = db.p;
+    const uint32_t P = p.n * p.nprimes;
+    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, rows, rows, P, db.mfma.kp, 0, p.d0, p.d0, st, mstride,
+                        row0);
 }
 
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st) {
-    const auto &p = db.p;
-    const uint32_t m_rows = 2 * B;
-    const uint32_t mp = (m_rows + 31) / 32 * 32;
-    const uint32_t P = p.n * p.nprimes;
-    const uint32_t kp = db.mfma.kp;
+    // scratch: query digit planes [P][4][Kp/64][Mp][64], then the output
+    // staging [P/4][Mp][D1][4]
+    const uint32_t mp = (2 * B + 31) / 32 * 32;
+    const size_t qbytes = (mfma_query_scratch_bytes(db, B) + 255) / 256 * 256;
+    const size_t sbytes = (size_t)db.slots() * mp * db.p.d1 * 4;
+    int8_t *scratch = nullptr;
+    PIR_HIP(hipMallocAsync((void **)&scratch, qbytes + sbytes, st));
+    uint32_t *stage = reinterpret_cast<uint32_t *>(scratch + qbytes);
+    launch_query_digits(db, q, B, scratch, st);
+    const MfmaJob job = make_mfma_job(db, scratch, stage, B, 0, pick_wm(B));
+    launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
+    launch_out_transpose(stage, out, 2 * B, mp, db.p.d1, (uint32_t)db.slots(), st);
+    PIR_HIP(hipFreeAsync(scratch, st));
+}
 
-    // query ingest: [B][2][D0][L][N] -> [P][4][Kp/64][Mp][64] digit planes
-    int8_t *qd = nullptr;
-    const size_t qbytes = mfma_query_scratch_bytes(db, B);
-    PIR_HIP(hipMallocAsync((void **)&qd, qbytes, st));
-    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, mp, m_rows, P, kp, 0, p.d0, p.d0, st);
+// ------------------------------------------------------------- grouped
+// A grouped launch keeps, per distinct set of (DB, batch) items, a plan with
+// the device job table and the scratch of every item (query digit planes and
+// output staging).  The first call for a set allocates it; later calls only
+// enqueue kernels (and may therefore be captured into a hipGraph).
+struct GroupPlan {
+    std::vector<std::pair<const pir_db *, uint32_t>> key;
+    int device = 0;
+    uint32_t wm = 4;
+    int8_t *scratch = nullptr;
+    MfmaJob *jobs_dev = nullptr;
+    std::vector<MfmaJob> jobs;
+    std::vector<size_t> item_job;   // item -> job index, or SIZE_MAX for B = 0
+    uint32_t total_tiles = 0;
+    ~GroupPlan() {
+        if (scratch) {
+            (void)hipSetDevice(device);
+            (void)hipDeviceSynchronize();
+            dev_free(scratch);
+        }
+    }
+};
 
-    ModQ4m mods{};
-    for (uint32_t l = 0; l < p.nprimes; ++l) mods.m[l] = db.mod[l];
-    launch_tile(pick_tile(mp), db, qd, out, m_rows, mp, mods, st);
-    PIR_HIP(hipFreeAsync(qd, st));
+static std::mutex g_plan_mu;
+static std::list<GroupPlan> g_plans;   // most recently used first
+constexpr size_t MAX_PLANS = 8;
+
+uint32_t pick_group_wm(const pir_rowsel_item *items, uint32_t count) {
+    if (const char *e = std::getenv("PIR_MFMA_WM")) {
+        const int v = std::atoi(e);
+        if (v == 2 || v == 4) return (uint32_t)v;
+    }
+    // the shape that wastes fewer padded rows over the whole group
+    uint64_t waste4 = 0, waste2 = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!items[i].B) continue;
+        const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32, d1 = items[i].db->p.d1;
+        const uint64_t m4 = (mp + 127) / 128 * 128, n4 = (d1 + 63) / 64 * 64;
+        const uint64_t m2 = (mp + 63) / 64 * 64, n2 = (d1 + 127) / 128 * 128;
+        const uint64_t w = (uint64_t)items[i].db->mfma.kp * items[i].db->slots();
+        waste4 += (m4 * n4 - mp * d1) * w;
+        waste2 += (m2 * n2 - mp * d1) * w;
+    }
+    return waste4 <= waste2 ? 4u : 2u;
+}
+
+static GroupPlan &get_plan(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
+    std::vector<std::pair<const pir_db *, uint32_t>> key(count);
+    for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
+    const uint32_t wm = pick_group_wm(items, count);
+    int dev = 0;
+    PIR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+        if (it->key == key && it->wm == wm && it->device == dev) {
+            g_plans.splice(g_plans.begin(), g_plans, it);
+            return g_plans.front();
+        }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    PIR_HIP(hipStreamIsCapturing(st, &cap));
+    PIR_REQUIRE(cap == hipStreamCaptureStatusNone,
+                "pir_rowsel_grouped: the first call for a set of item shapes allocates and cannot be captured");
+    g_plans.emplace_front();
+    GroupPlan &pl = g_plans.front();
+    pl.key = key;
+    pl.device = dev;
+    pl.wm = wm;
+    // layout of the scratch: per job [query digits][staging], then the job table
+    std::vector<size_t> qoff, soff;
+    size_t bytes = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!items[i].B) {
+            qoff.push_back(0);
+            soff.push_back(0);
+            continue;
+        }
+        const pir_db &db = *items[i].db;
+        const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32;
+        qoff.push_back(bytes);
+        bytes += (mfma_query_scratch_bytes(db, items[i].B) + 255) / 256 * 256;
+        soff.push_back(bytes);
+        bytes += ((size_t)db.slots() * mp * db.p.d1 * 4 + 255) / 256 * 256;
+    }
+    const size_t jobs_off = bytes;
+    bytes += sizeof(MfmaJob) * count + 256;
+    pl.scratch = static_cast<int8_t *>(dev_alloc(bytes));
+    uint32_t tile0 = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!items[i].B) {
+            pl.item_job.push_back(SIZE_MAX);
+            continue;
+        }
+        pl.item_job.push_back(pl.jobs.size());
+        MfmaJob j = make_mfma_job(*items[i].db, pl.scratch + qoff[i],
+                                  reinterpret_cast<uint32_t *>(pl.scratch + soff[i]), items[i].B, tile0, wm);
+        tile0 += j.tiles;
+        pl.jobs.push_back(j);
+    }
+    pl.total_tiles = tile0;
+    pl.jobs_dev = reinterpret_cast<MfmaJob *>(pl.scratch + jobs_off);
+    if (!pl.jobs.empty())
+        PIR_HIP(hipMemcpy(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(), hipMemcpyHostToDevice));
+    while (g_plans.size() > MAX_PLANS) g_plans.pop_back();
+    return g_plans.front();
+}
+
+void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
+    GroupPlan &pl = get_plan(items, count, st);
+    if (pl.jobs.empty()) return;
+    for (uint32_t i = 0; i < count; ++i)
+        if (pl.item_job[i] != SIZE_MAX)
+            launch_query_digits(*items[i].db, items[i].q_dev, items[i].B,
+                                const_cast<int8_t *>(pl.jobs[pl.item_job[i]].qd), st);
+    launch_mfma_jobs(pl.jobs[0], pl.jobs_dev, (uint32_t)pl.jobs.size(), pl.total_tiles, st);
+    for (uint32_t i = 0; i < count; ++i) {
+        if (pl.item_job[i] == SIZE_MAX) continue;
+        const MfmaJob &j = pl.jobs[pl.item_job[i]];
+        launch_out_transpose(j.out, items[i].out_dev, j.m_rows, j.mp, j.d1, (uint32_t)items[i].db->slots(), st);
+    }
+}
+
+void release_group_plans() {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plans.clear();
 }
 
 }  // namespace pir

@@ -1,0 +1,338 @@
+// Continuous-batching RowSel server: a native host loop around the MFMA
+// kernels.
+//
+// The DB's L*N/4 point groups are swept in `chunks` steps.  Client slot s
+// owns rows 2s and 2s+1 of one shared set of query digit planes
+// [L*N][4][Kp/64][mstride][64]; a step runs the persistent MFMA RowSel on one
+// chunk of point groups for rows [0, 2*(highest active slot + 1)) and
+// scatters each row's results to its request's output buffer.  A request is
+// admitted into a free slot at a step boundary, takes part in the next
+// `chunks` steps (one full sweep, starting wherever the sweep is) and then
+// completes; every output word depends only on its own slot's rows, so
+// results do not depend on the mix.  Slots pass FREE -> ACTIVE -> DRAINING
+// (last step launched; its output pointers are cleared on the stream right
+// away, so later steps cannot write to it) -> FREE (last step retired).
+#include <chrono>
+#include <deque>
+#include <vector>
+
+#include "common.h"
+#include "mfma.h"
+
+namespace pir {
+
+// Staging [cg][mp][d1][4] of one step -> per-row destinations.  Row m holds
+// slot m/2, component m%2; row_dst[m] is that component's [D1][L*N/4] array
+// of 16-byte vectors (0 = discard).  A block takes one row, 32 columns and
+// 32 point groups and moves 512-byte runs on both sides.
+__global__ void __launch_bounds__(256)
+serve_scatter_kernel(const uint4 *__restrict__ stage, const uint64_t *__restrict__ row_dst, uint32_t mp,
+                     uint32_t d1, uint32_t cg, uint32_t g_begin, uint32_t gall, uint32_t nblk_n,
+                     uint32_t nblk_g) {
+    __shared__ uint4 tile[32][33];
+    const uint32_t tid = threadIdx.x;
+    uint32_t b = blockIdx.x;
+    const uint32_t gb = b % nblk_g;
+    b /= nblk_g;
+    const uint32_t nb = b % nblk_n;
+    const uint32_t m = b / nblk_n;
+    uint4 *dst = reinterpret_cast<uint4 *>(row_dst[m]);
+    if (!dst) return;   // uniform for the block
+    const uint32_t g0 = gb * 32, n0 = nb * 32;
+    for (uint32_t e = tid; e < 1024; e += 256) {
+        const uint32_t gi = e / 32, ni = e % 32;
+        if (g0 + gi < cg && n0 + ni < d1) tile[ni][gi] = stage[((uint64_t)(g0 + gi) * mp + m) * d1 + n0 + ni];
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < 1024; e += 256) {
+        const uint32_t ni = e / 32, gi = e % 32;
+        if (g0 + gi < cg && n0 + ni < d1) dst[(uint64_t)(n0 + ni) * gall + g_begin + g0 + gi] = tile[ni][gi];
+    }
+}
+
+// Writes up to ROW_UPDATES entries of the row-pointer table; the values travel
+// as kernel arguments, so no host buffer has to outlive the launch.
+constexpr int ROW_UPDATES = 32;
+struct RowUpdates {
+    uint32_t n;
+    uint32_t row[ROW_UPDATES];
+    uint64_t val[ROW_UPDATES];
+};
+
+__global__ void set_rows_kernel(uint64_t *row_dst, RowUpdates u) {
+    const uint32_t i = threadIdx.x;
+    if (i < u.n) row_dst[u.row[i]] = u.val[i];
+}
+
+static double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace pir
+
+using namespace pir;
+
+struct pir_server {
+    enum State : uint8_t { FREE, ACTIVE, DRAINING };
+    struct Slot {
+        State state = FREE;
+        uint64_t id = 0;
+        uint32_t remaining = 0;
+        double t_submit = 0, t_admit = 0;
+    };
+    struct Pending {
+        pir_request r;
+        double t_submit;
+    };
+    struct Step {
+        hipEvent_t ev;
+        std::vector<uint32_t> finishing;
+    };
+
+    const pir_db *db = nullptr;
+    int device = 0;
+    hipStream_t st = nullptr;
+    uint32_t capacity = 0, chunks = 0, pipeline = 2, cg = 0, gall = 0, mstride = 0;
+    uint64_t device_bytes = 0;
+    int8_t *qd = nullptr;
+    uint32_t *stage = nullptr;
+    uint64_t *row_dst_dev = nullptr;    // per row: destination of its results (0 = discard)
+    RowUpdates pending_rows{};          // table updates not yet launched
+    std::vector<Slot> slots;
+    std::deque<Pending> waitq;
+    std::deque<Step> inflight;
+    std::deque<pir_completion> done;
+    std::vector<hipEvent_t> spare_events;
+    uint64_t next_chunk = 0, steps = 0, admitted = 0, completed = 0;
+
+    ~pir_server() {
+        if (device_bytes || st) {
+            (void)hipSetDevice(device);
+            if (st) (void)hipStreamSynchronize(st);
+        }
+        for (auto &s : inflight) (void)hipEventDestroy(s.ev);
+        for (auto e : spare_events) (void)hipEventDestroy(e);
+        dev_free(qd);
+        dev_free(stage);
+        dev_free(row_dst_dev);
+        if (st) (void)hipStreamDestroy(st);
+    }
+
+    // device bytes for `cap` client slots
+    uint64_t bytes_for(uint32_t cap) const {
+        const uint64_t P = db->slots(), ms = (2ull * cap + 127) / 128 * 128;
+        return P * 4 * db->mfma.kp * ms + (uint64_t)cg * ms * db->p.d1 * 16 + ms * 8 + 4096;
+    }
+
+    void flush_rows() {
+        if (!pending_rows.n) return;
+        set_rows_kernel<<<1, ROW_UPDATES, 0, st>>>(row_dst_dev, pending_rows);
+        PIR_LAUNCH_CHECK();
+        pending_rows.n = 0;
+    }
+
+    void set_rows(uint32_t s, const uint32_t *out) {
+        const uint64_t comp = out ? (uint64_t)db->p.d1 * db->slots() : 0;   // words per component
+        if (pending_rows.n + 2 > ROW_UPDATES) flush_rows();
+        RowUpdates &u = pending_rows;
+        u.row[u.n] = 2 * s;
+        u.val[u.n++] = out ? reinterpret_cast<uint64_t>(out) : 0;
+        u.row[u.n] = 2 * s + 1;
+        u.val[u.n++] = out ? reinterpret_cast<uint64_t>(out + comp) : 0;
+    }
+
+    void retire() {
+        while (!inflight.empty()) {
+            const hipError_t e = hipEventQuery(inflight.front().ev);
+            if (e == hipErrorNotReady) {
+                (void)hipGetLastError();   // not an error: clear it
+                break;
+            }
+            if (e != hipSuccess) PIR_FAIL(PIR_EDEVICE, "serving step failed: %s", hipGetErrorString(e));
+            const double t = now_s();
+            for (uint32_t s : inflight.front().finishing) {
+                Slot &sl = slots[s];
+                done.push_back(pir_completion{sl.id, PIR_OK, 0, sl.t_submit, sl.t_admit, t});
+                sl.state = FREE;
+                ++completed;
+            }
+            spare_events.push_back(inflight.front().ev);
+            inflight.pop_front();
+        }
+    }
+
+    void admit() {
+        for (uint32_t s = 0; s < capacity && !waitq.empty(); ++s) {
+            if (slots[s].state != FREE) continue;
+            const Pending pr = waitq.front();
+            waitq.pop_front();
+            Slot &sl = slots[s];
+            sl.state = ACTIVE;
+            sl.id = pr.r.id;
+            sl.remaining = chunks;
+            sl.t_submit = pr.t_submit;
+            sl.t_admit = now_s();
+            launch_query_digits_rows(*db, pr.r.q_dev, 2, qd, mstride, 2 * s, st);
+            set_rows(s, pr.r.out_dev);
+            ++admitted;
+        }
+        flush_rows();
+    }
+
+    // launches the next step if any client is active; returns false otherwise
+    bool launch_step() {
+        uint32_t hi = 0;
+        bool any = false;
+        for (uint32_t s = 0; s < capacity; ++s)
+            if (slots[s].state == ACTIVE) {
+                hi = s;
+                any = true;
+            }
+        if (!any) return false;
+        const uint32_t rows = 2 * (hi + 1);
+        const uint32_t c = (uint32_t)(next_chunk++ % chunks);
+        const uint32_t g_begin = c * cg, ng = std::min(cg, gall - g_begin);
+        MfmaJob job = make_mfma_job(*db, qd, stage, hi + 1, 0, pick_wm(hi + 1));
+        job.mstride = mstride;
+        job.g_begin = g_begin;
+        job.groups = ng;
+        job.tiles = ng * job.nblk_m * job.nblk_n;
+        launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
+        const uint32_t nblk_n = (db->p.d1 + 31) / 32, nblk_g = (ng + 31) / 32;
+        const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_g;
+        serve_scatter_kernel<<<(uint32_t)blocks, 256, 0, st>>>(reinterpret_cast<const uint4 *>(stage), row_dst_dev,
+                                                               job.mp, db->p.d1, ng, g_begin, gall, nblk_n, nblk_g);
+        PIR_LAUNCH_CHECK();
+        Step step;
+        for (uint32_t s = 0; s < capacity; ++s) {
+            Slot &sl = slots[s];
+            if (sl.state != ACTIVE) continue;
+            if (--sl.remaining == 0) {
+                sl.state = DRAINING;
+                step.finishing.push_back(s);
+                set_rows(s, nullptr);   // later steps must not write to this request any more
+            }
+        }
+        flush_rows();
+        if (spare_events.empty()) {
+            hipEvent_t e;
+            PIR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            spare_events.push_back(e);
+        }
+        step.ev = spare_events.back();
+        spare_events.pop_back();
+        PIR_HIP(hipEventRecord(step.ev, st));
+        inflight.push_back(std::move(step));
+        ++steps;
+        return true;
+    }
+};
+
+extern "C" {
+
+double pir_clock(void) { return now_s(); }
+
+pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_server **out) {
+    return guarded([&] {
+        PIR_REQUIRE(db && out, "NULL argument");
+        *out = nullptr;
+        PIR_REQUIRE(db->layouts & PIR_LAYOUT_MFMA, "the server needs a DB with the MFMA layout");
+        pir_server_opts o{};
+        if (opts) o = *opts;
+        const uint32_t max_clients = o.max_clients ? o.max_clients : 256;
+        PIR_REQUIRE(max_clients <= 4096, "max_clients must be <= 4096");
+        PIR_REQUIRE(o.pipeline <= 4, "pipeline must be 1..4");
+        PIR_HIP(hipSetDevice(db->device));
+        auto *srv = new pir_server();
+        try {
+            srv->db = db;
+            srv->device = db->device;
+            srv->pipeline = o.pipeline ? o.pipeline : 2;
+            srv->gall = (uint32_t)(db->slots() / 4);
+            uint32_t chunks = o.chunks ? o.chunks : 16;
+            PIR_REQUIRE(chunks <= srv->gall, "chunks must be <= L*N/4 = %u", srv->gall);
+            srv->cg = (srv->gall + chunks - 1) / chunks;
+            srv->chunks = (srv->gall + srv->cg - 1) / srv->cg;
+            uint64_t budget = o.hbm_budget;
+            if (!budget) {
+                size_t fr = 0, tot = 0;
+                PIR_HIP(hipMemGetInfo(&fr, &tot));
+                budget = (uint64_t)(fr * 0.9);
+            }
+            uint32_t cap = max_clients;
+            while (cap > 0 && srv->bytes_for(cap) > budget) cap = cap > 64 ? cap - cap / 16 : cap - 1;
+            if (!cap) PIR_FAIL(PIR_ENOMEM, "budget of %llu bytes holds no client (one needs %llu)",
+                               (unsigned long long)budget, (unsigned long long)srv->bytes_for(1));
+            srv->capacity = cap;
+            srv->mstride = (2 * cap + 127) / 128 * 128;
+            const uint64_t P = db->slots();
+            srv->qd = static_cast<int8_t *>(dev_alloc(P * 4 * db->mfma.kp * srv->mstride));
+            srv->stage = static_cast<uint32_t *>(dev_alloc((uint64_t)srv->cg * srv->mstride * db->p.d1 * 16));
+            srv->row_dst_dev = static_cast<uint64_t *>(dev_alloc((uint64_t)srv->mstride * 8));
+            srv->device_bytes = srv->bytes_for(cap);
+            // every row starts as "discard"; query rows start zeroed
+            PIR_HIP(hipMemset(srv->qd, 0, P * 4 * db->mfma.kp * srv->mstride));
+            PIR_HIP(hipMemset(srv->row_dst_dev, 0, (size_t)srv->mstride * 8));
+            PIR_HIP(hipDeviceSynchronize());
+            PIR_HIP(hipStreamCreateWithFlags(&srv->st, hipStreamNonBlocking));
+            srv->slots.resize(cap);
+        } catch (...) {
+            delete srv;
+            throw;
+        }
+        *out = srv;
+    });
+}
+
+pir_status pir_serve_step(pir_server *srv, const pir_request *arrivals, uint32_t n_arrivals,
+                          pir_completion *done, uint32_t cap, uint32_t *n_done) {
+    return guarded([&] {
+        PIR_REQUIRE(srv != nullptr, "server is NULL");
+        PIR_REQUIRE(n_arrivals == 0 || arrivals != nullptr, "arrivals is NULL");
+        PIR_REQUIRE(cap == 0 || done != nullptr, "done is NULL");
+        if (n_done) *n_done = 0;
+        PIR_HIP(hipSetDevice(srv->device));
+        const double t = now_s();
+        const auto &p = srv->db->p;
+        const size_t qb = (size_t)2 * p.d0 * srv->db->slots() * 4, ob = (size_t)2 * p.d1 * srv->db->slots() * 4;
+        for (uint32_t i = 0; i < n_arrivals; ++i) {
+            const pir_request &r = arrivals[i];
+            const auto qa = reinterpret_cast<uintptr_t>(r.q_dev), oa = reinterpret_cast<uintptr_t>(r.out_dev);
+            const bool bad = !r.q_dev || !r.out_dev || qa % 16 || oa % 16 || (qa < oa + ob && oa < qa + qb);
+            if (bad) srv->done.push_back(pir_completion{r.id, PIR_EINVAL, 0, t, t, t});
+            else srv->waitq.push_back({r, t});
+        }
+        srv->retire();
+        while (srv->inflight.size() < srv->pipeline) {
+            srv->admit();
+            if (!srv->launch_step()) break;
+        }
+        uint32_t k = 0;
+        while (k < cap && !srv->done.empty()) {
+            done[k++] = srv->done.front();
+            srv->done.pop_front();
+        }
+        if (n_done) *n_done = k;
+    });
+}
+
+pir_status pir_server_get_stats(const pir_server *srv, pir_server_stats *out) {
+    return guarded([&] {
+        PIR_REQUIRE(srv && out, "NULL argument");
+        pir_server_stats s{};
+        s.capacity = srv->capacity;
+        for (const auto &sl : srv->slots) s.active += sl.state == pir_server::ACTIVE;
+        s.waiting = (uint32_t)srv->waitq.size();
+        s.inflight = (uint32_t)srv->inflight.size();
+        s.steps = srv->steps;
+        s.admitted = srv->admitted;
+        s.completed = srv->completed;
+        s.device_bytes = srv->device_bytes;
+        *out = s;
+    });
+}
+
+void pir_server_destroy(pir_server *srv) { delete srv; }
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+"""GPU tests of the continuous-batching server: every completed request's
+output equals the oracle's RowSel of its query, a request gives the same
+bits alone and in a mix, requests arriving while others run are admitted,
+malformed requests fail alone, and the HBM budget bounds the capacity."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import empty_u32, np_u32, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N, PR, D0, D1 = 64, synth.PRIMES_N4096, 40, 50
+
+
+@pytest.fixture(scope="module")
+def pir():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_04696_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def served(pir):
+    coeffs = synth.db_coeffs(80, D0, D1, 2, N)
+    dhat = oracle.ntt_db(coeffs, PR)
+    db = pir.pir_db_create(pir.make_params(N, PR, D0, D1), pir.PIR_LAYOUT_MFMA)
+    pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+    torch.cuda.synchronize()
+    queries = synth.query_uniform(81, 12, D0, PR, N)          # 12 distinct clients
+    wants = oracle.rowsel(queries, dhat, PR)
+    return db, queries, wants
+
+
+def run_until(pir, srv, schedule, expect, timeout=60.0):
+    """schedule: {turn: [(id, q, out), ...]}; loops serve_step until `expect`
+    completions arrived."""
+    got, turn, t0 = {}, 0, time.time()
+    while len(got) < expect:
+        for c in pir.pir_serve_step(srv, schedule.get(turn, ())):
+            got[c.id] = c
+        turn += 1
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"only {len(got)} of {expect} completions")
+    return got
+
+
+def test_serve_matches_oracle_with_staggered_arrivals(pir, served):
+    db, queries, wants = served
+    srv = pir.pir_server_create(db, max_clients=4, chunks=4, pipeline=2)
+    outs = [empty_u32(2 * D1 * 2 * N) for _ in range(12)]
+    qs = [to_dev(queries[i]) for i in range(12)]
+    # requests arrive over several turns, while earlier ones are on the GPU
+    schedule = {0: [(i, qs[i], outs[i]) for i in range(5)],
+                1: [(i, qs[i], outs[i]) for i in range(5, 8)],
+                3: [(i, qs[i], outs[i]) for i in range(8, 12)]}
+    got = run_until(pir, srv, schedule, 12)
+    torch.cuda.synchronize()
+    st = pir.pir_server_get_stats(srv)
+    assert st.capacity == 4 and st.admitted == 12 and st.completed == 12
+    for i in range(12):
+        c = got[i]
+        assert c.status == 0
+        assert c.t_submit <= c.t_admit <= c.t_done
+        assert np.array_equal(np_u32(outs[i]).reshape(wants[i].shape), wants[i]), f"request {i}"
+    pir.pir_server_destroy(srv)
+
+
+def test_serve_alone_equals_in_mix(pir, served):
+    db, queries, wants = served
+    q7 = to_dev(queries[7])
+    alone = empty_u32(2 * D1 * 2 * N)
+    srv = pir.pir_server_create(db, max_clients=8, chunks=3)
+    run_until(pir, srv, {0: [(7, q7, alone)]}, 1)
+    pir.pir_server_destroy(srv)
+    srv = pir.pir_server_create(db, max_clients=8, chunks=3)
+    outs = {i: empty_u32(2 * D1 * 2 * N) for i in range(12)}
+    schedule = {0: [(i, to_dev(queries[i]), outs[i]) for i in (0, 3, 9)],
+                2: [(7, q7, outs[7])] + [(i, to_dev(queries[i]), outs[i]) for i in (1, 11, 4)]}
+    run_until(pir, srv, schedule, 7)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, outs[7])
+    assert np.array_equal(np_u32(alone).reshape(wants[7].shape), wants[7])
+    pir.pir_server_destroy(srv)
+
+
+def test_serve_bad_request_fails_alone(pir, served):
+    db, queries, wants = served
+    srv = pir.pir_server_create(db, max_clients=2, chunks=2)
+    good = empty_u32(2 * D1 * 2 * N)
+    bad = empty_u32(2 * max(D0, D1) * 2 * N)      # query and output are the same buffer
+    got = run_until(pir, srv, {0: [(1, bad, bad), (2, to_dev(queries[2]), good)]}, 2)
+    assert got[1].status == pir.PIR_EINVAL
+    assert got[2].status == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(np_u32(good).reshape(wants[2].shape), wants[2])
+    pir.pir_server_destroy(srv)
+
+
+def test_serve_budget_bounds_capacity(pir, served):
+    db, queries, wants = served
+    big = pir.pir_server_create(db, max_clients=256)
+    per_all = pir.pir_server_get_stats(big).device_bytes
+    assert pir.pir_server_get_stats(big).capacity == 256
+    pir.pir_server_destroy(big)
+    small = pir.pir_server_create(db, max_clients=256, hbm_budget=per_all // 3)
+    st = pir.pir_server_get_stats(small)
+    assert 0 < st.capacity < 256 and st.device_bytes <= per_all // 3
+    outs = [empty_u32(2 * D1 * 2 * N) for _ in range(6)]
+    got = run_until(pir, small, {0: [(i, to_dev(queries[i]), outs[i]) for i in range(6)]}, 6)
+    torch.cuda.synchronize()
+    for i in range(6):
+        assert got[i].status == 0
+        assert np.array_equal(np_u32(outs[i]).reshape(wants[i].shape), wants[i])
+    pir.pir_server_destroy(small)
+    with pytest.raises(pir.PirError, match="holds no client"):
+        pir.pir_server_create(db, max_clients=4, hbm_budget=1024)
