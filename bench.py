@@ -5,13 +5,20 @@ N = 4096, two-prime, 512 x 512 NTT-domain database of 16-bit coefficients
 (8 GiB), through the C ABI, VALU streaming path.  A step is one pir_rowsel
 call (query in HBM -> output in HBM).  value = DB bytes streamed per second.
 
-Extra figures on the same DB: 64 clients on the VALU and the INT8-MFMA
-paths.  Beside them: the CPU oracle timed on a bounded sample of the
-headline workload, and the roofline of the dominant kernel.
+Further figures in the same line:
+  batched_b64  64 clients on the same DB, VALU and INT8-MFMA paths;
+  grouped      24 uneven instances (own DBs) in one pir_rowsel_grouped call,
+               eager and replayed from a captured hipGraph;
+  serving      a 1024 x 1024 (32 GiB) DB behind pir_serve_step, Poisson
+               arrivals, queries/s and p50/p99 latency;
+  cpu_baseline the CPU oracle on a bounded sample of the headline workload;
+  roofline     of the headline kernel (traffic from the committed counter
+               summary when the kernel source is unchanged since it was taken).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -69,6 +76,144 @@ def timed_calls(fn, reps):
     return [a.elapsed_time(b) for a, b in ev]
 
 
+PROFILE = os.path.join(ROOT, "profiles", "rowsel_stream_kernel_n4096_l2_512x512_b1.md")
+STREAM_SRC = os.path.join(ROOT, "paper_2604_04696_amd", "csrc", "rowsel_valu.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, or None when the kernel source changed since it was measured."""
+    try:
+        text = open(PROFILE).read()
+        rec = json.loads(text.split("<!-- traffic ")[1].split(" -->")[0])
+        sha = hashlib.sha256(open(STREAM_SRC, "rb").read()).hexdigest()
+        return rec["traffic_bytes"] if rec["source_sha256"] == sha else None
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
+def grouped_section(pir, reps: int):
+    """24 uneven instances in one pir_rowsel_grouped call (MFMA path)."""
+    import torch
+    import synth
+    insts = synth.grouped_instances()
+    items, macs, dbb = [], 0, 0
+    for it in insts:
+        w = synth.Workload(f"g{it.index}", it.seed, it.n, it.primes, it.d0, it.d1, it.clients, "uniform")
+        db = pir.pir_db_create(pir.make_params(it.n, it.primes, it.d0, it.d1), pir.PIR_LAYOUT_MFMA)
+        key = synth.stream_key(it.seed, synth.TAG_DB, it.index)
+        per_row = it.d1 * 2 * it.n
+        buf = torch.empty(it.d0 * per_row, dtype=torch.int32, device="cuda")
+        pir.pir_synth_db_coeffs(buf, key, 0, it.d0, it.d1, 2, it.n)
+        pir.pir_db_load_ntt(db, buf, 0, it.d0, pir.PIR_DOMAIN_COEFF)
+        del buf
+        q = torch.empty(it.clients * 2 * it.d0 * w.slots, dtype=torch.int32, device="cuda")
+        pir.pir_synth_query(q, synth.stream_key(it.seed, synth.TAG_QUERY, it.index), 0, it.clients, it.d0,
+                            it.primes, it.n)
+        out = torch.empty(it.clients * 2 * it.d1 * w.slots, dtype=torch.int32, device="cuda")
+        items.append((db, q, it.clients, out))
+        macs += w.macs
+        dbb += w.db_bytes
+    fn = lambda: pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    fn()
+    torch.cuda.synchronize()
+    eager = statistics.median(timed_calls(fn, reps))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        fn()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    graph = statistics.median(timed_calls(g.replay, reps))
+    res = {"instances": len(insts), "mod_macs": macs, "db_gib": round(dbb / 2**30, 2),
+           "eager_ms": round(eager, 3), "graph_ms": round(graph, 3),
+           "mac_per_s": macs / (graph * 1e-3), "db_gbs": round(dbb / (graph * 1e-3) / 1e9, 1),
+           "launches": 2 * len(insts) + 1}
+    tm, tn = pir.pir_rowsel_grouped_tile(items)
+    res["tile"] = f"{tm}x{tn} (timed at plan build)"
+    del g
+    for db, q, B, out in items:
+        pir.pir_db_free(db)
+    return res
+
+
+def serving_section(pir, n_requests: int, loads):
+    """pir_serve_step over the 1024 x 1024 DB: saturated throughput with the
+    admission cap full, then seeded Poisson streams at each of `loads` x
+    that rate."""
+    import numpy as np
+    import torch
+    import synth
+    w = synth.SERVE_DB
+    db = build_db(pir, w, pir.PIR_LAYOUT_MFMA)
+    pool = [make_query_sub(pir, w, i) for i in range(32)]
+    nring = 512
+    outs = [torch.empty(2 * w.d1 * w.slots, dtype=torch.int32, device="cuda") for _ in range(nring)]
+    chunks = 16
+    srv = pir.pir_server_create(db, max_clients=256, chunks=chunks, pipeline=2)
+    cap = pir.pir_server_get_stats(srv).capacity
+
+    def drive(arrival_times, choice):
+        """Feeds each request at its scheduled arrival time (host clock of
+        the library); returns completions, the start time, the span and the
+        number of active clients after every step."""
+        t0 = pir.pir_clock()
+        nxt, got, active = 0, [], []
+        while len(got) < len(arrival_times):
+            now = pir.pir_clock() - t0
+            batch = []
+            while nxt < len(arrival_times) and arrival_times[nxt] <= now:
+                batch.append((nxt, pool[choice[nxt]], outs[nxt % nring]))
+                nxt += 1
+            got += pir.pir_serve_step(srv, batch)
+            active.append(pir.pir_server_get_stats(srv).active)
+        return got, t0, pir.pir_clock() - t0, active
+
+    # saturated: twice the admission cap arrives at once
+    sat_n = 2 * cap
+    got, _, dt, _ = drive(np.zeros(sat_n), np.arange(sat_n) % 32)
+    qps_sat = sat_n / dt
+    runs = []
+    same = True
+    for load in loads:
+        lam = load * qps_sat
+        arr = synth.poisson_arrivals(w.seed, lam, n_requests)
+        choice = synth.pool_choice(w.seed, n_requests)
+        got, t0, dt, active = drive(arr, choice)
+        # latency from the scheduled arrival (includes the wait for the next step)
+        lat = np.array([c.t_done - (t0 + arr[c.id]) for c in got])
+        edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 4097]
+        hist = np.histogram(np.array(active), bins=edges)[0]
+        runs.append({"load": load, "offered_qps": round(lam, 1), "requests": n_requests,
+                     "qps": round(n_requests / dt, 1),
+                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                     "all_ok": all(c.status == 0 for c in got),
+                     "active_per_step_hist": {f"{a}-{b - 1}": int(h) for a, b, h in zip(edges, edges[1:], hist) if h}})
+        # the last requests' outputs against the same query served alone
+        torch.cuda.synchronize()
+        for c in sorted(got, key=lambda c: c.id)[-4:]:
+            ref = torch.empty_like(outs[0])
+            pir.pir_rowsel(db, pool[choice[c.id]], ref, pir.PIR_PATH_MFMA_I8)
+            torch.cuda.synchronize()
+            same = same and torch.equal(ref, outs[c.id % nring])
+    st = pir.pir_server_get_stats(srv)
+    pir.pir_server_destroy(srv)
+    pir.pir_db_free(db)
+    return {"workload": w.name, "capacity": cap, "chunks": chunks, "saturated_qps": round(qps_sat, 1),
+            "runs": runs, "in_mix_equals_alone": same, "steps": st.steps}
+
+
+def make_query_sub(pir, w, sub):
+    import torch
+    import synth
+    q = torch.empty(2 * w.d0 * w.slots, dtype=torch.int32, device="cuda")
+    pir.pir_synth_query(q, synth.stream_key(w.seed, synth.TAG_POOL, sub), 0, 1, w.d0, w.primes, w.n)
+    return q
+
+
 def cpu_baseline(w, target_s: float):
     """The oracle (unmodified) on a bounded sample of the headline workload:
     all 512 rows and all 8192 points of a subset of DB columns, one client,
@@ -100,6 +245,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-client figures")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the grouped-instances figures")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving figures")
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-loads", default="0.7,0.9",
+                    help="offered loads as fractions of the saturated rate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calib", action="store_true",
@@ -174,7 +324,7 @@ def main():
                    "clients": 1, "path": "VALU", "db_gib": w.db_bytes / 2**30},
         "mac_per_s": w.macs / (ms_step * 1e-3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "rowsel_stream_kernel<2>", "kernel_ms": round(kmean, 4),
                      "alg_bytes_per_launch": alg_bytes},
     }
@@ -199,11 +349,27 @@ def main():
         line["batched_b64"] = res
         del qb, ob
 
+    pir.pir_db_free(db)
+    del q1, out1
+    torch.cuda.empty_cache()
+
+    if not args.no_grouped:
+        log("grouped instances")
+        line["grouped"] = grouped_section(pir, reps=5)
+        torch.cuda.empty_cache()
+        log(f"grouped: {line['grouped']}")
+
+    if not args.no_serve:
+        log("serving")
+        line["serving"] = serving_section(pir, args.serve_requests,
+                                          [float(x) for x in args.serve_loads.split(",")])
+        torch.cuda.empty_cache()
+        log(f"serving: {line['serving']}")
+
     if not args.no_cpu:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
 
-    pir.pir_db_free(db)
     print(json.dumps(line), flush=True)
 
 

@@ -154,9 +154,21 @@ typedef struct {
  * work table and scratch, kept for reuse; up to 8 plans are cached) and must
  * not be made while the stream is being captured (PIR_EINVAL); later calls
  * with the same list only enqueue kernels and may be captured into a
- * hipGraph, with any query/output pointers. */
+ * hipGraph, with any query/output pointers.  When the plan is built, both
+ * output tile shapes of the persistent kernel (128 x 64 and 64 x 128) run
+ * once on the call's inputs, timed on its stream (the first call therefore
+ * synchronizes the stream), and the faster one is kept; PIR_MFMA_WM=4 or 2
+ * in the environment forces one shape, PIR_AUTOTUNE=0 picks the shape that
+ * pads fewer rows without timing. */
 pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count,
                               pir_path path, void *hip_stream);
+
+/* Output tile (rows x columns of the GEMM) chosen for the cached MFMA plan of
+ * an item list, as built by a previous pir_rowsel_grouped call with the
+ * same list of (db, B).  Only the (db, B) pairs of `items` are read.
+ * PIR_EINVAL if no plan exists for the list or an out pointer is NULL. */
+pir_status pir_rowsel_grouped_tile(const pir_rowsel_item *items, uint32_t count,
+                                   uint32_t *tile_m, uint32_t *tile_n);
 
 /* ---------------------------------------------------------------- serving */
 /* A RowSel server over one resident DB with continuous batching.  The DB's

@@ -57,6 +57,7 @@ SIGNATURES = {
     "pir_db_free": (None, [_vp]),
     "pir_rowsel": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
     "pir_rowsel_grouped": (_i32, [_vp, _u32, _i32, _vp]),
+    "pir_rowsel_grouped_tile": (_i32, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "pir_clock": (ctypes.c_double, []),
     "pir_server_create": (_i32, [_vp, _vp, ctypes.POINTER(_vp)]),
     "pir_serve_step": (_i32, [_vp, _vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]),
@@ -229,6 +230,17 @@ def pir_rowsel_grouped(items, path: int = PIR_PATH_AUTO, stream=None):
         arr[i].out_dev = _ptr(out, "out") if B else None
     _check(lib().pir_rowsel_grouped(ctypes.cast(arr, ctypes.c_void_p), len(items), path,
                                     _stream(stream)), "pir_rowsel_grouped")
+
+
+def pir_rowsel_grouped_tile(items):
+    """(rows, cols) of the output tile kept for the plan of this item list."""
+    arr = (pir_rowsel_item * max(1, len(items)))()
+    for i, (db, q, B, out) in enumerate(items):
+        arr[i].db, arr[i].B = db.handle, B
+    tm, tn = _u32(), _u32()
+    _check(lib().pir_rowsel_grouped_tile(ctypes.cast(arr, ctypes.c_void_p), len(items), ctypes.byref(tm),
+                                         ctypes.byref(tn)), "pir_rowsel_grouped_tile")
+    return tm.value, tn.value
 
 
 # ---------------------------------------------------------------- serving

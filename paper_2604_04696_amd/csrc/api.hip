@@ -338,6 +338,15 @@ pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count, pir_
     });
 }
 
+pir_status pir_rowsel_grouped_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *tile_m,
+                                   uint32_t *tile_n) {
+    return guarded([&] {
+        PIR_REQUIRE(tile_m != nullptr && tile_n != nullptr, "NULL argument");
+        PIR_REQUIRE(count == 0 || items != nullptr, "items is NULL");
+        PIR_REQUIRE(group_plan_tile(items, count, tile_m, tile_n), "no grouped plan for this item list");
+    });
+}
+
 static pir_status ntt_entry(const uint32_t *in, uint32_t *out, uint32_t count, uint32_t n, uint32_t q,
                             void *stream, bool inverse) {
     return guarded([&] {

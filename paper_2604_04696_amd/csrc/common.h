@@ -163,6 +163,8 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st);
 void release_group_plans();
+// Tile (rows x columns) of the cached grouped plan of an item set; false if none.
+bool group_plan_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *bm, uint32_t *bn);
 void check_rowsel_args(const pir_db *db, const uint32_t *q, uint32_t B, const uint32_t *out);
 void rowsel_one(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, pir_path path,
                 hipStream_t st);

@@ -16,12 +16,13 @@ struct EpiQ {
 struct MfmaJob {
     const int8_t *qd;      // query digit planes [L*N][4][nkc][mstride][64]
     const int8_t *dbd;     // DB digit planes    [L*N][4][nkc][d1][64]
-    uint32_t *out;         // staging [groups][mp][d1][4] (see out_transpose_kernel)
+    uint32_t *out;         // staging [points][mp][d1] (see out_transpose_kernel)
     uint32_t m_rows, mp, d1, nkc, L, N;
     uint32_t mstride;      // rows of a query plane (>= mp)
     uint32_t g_begin;      // first point group (groups of four points) of this job
     uint32_t wm;           // waves along m: 4 (128 x 64 tiles) or 2 (64 x 128 tiles)
     uint32_t nblk_m, nblk_n, groups, tile0, tiles;
+    uint32_t split;        // 1: some prime needs the split recombination (combine_classes)
     EpiQ q[PIR_MAX_PRIMES];
 };
 

@@ -58,30 +58,31 @@ __device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t q) 
     return a >= b ? a - b : a + q - b;
 }
 
-// Reduction of an exact integer held in binary64, |x| < 2^52, into [0, q):
-// t = floor(x * (1/q)) is the true quotient or off by one (the product's
-// relative error is below 2^-52 while the quotient is below 2^52/q), the
-// remainder x - t*q is exact in one FMA (both terms are integers below
-// 2^53), and one correction each way brings it into [0, q).
-template <class M>
-__device__ __forceinline__ double fp_reduce(double x, const M &m) {
-    const double t = floor(x * m.qinv);
-    double r = fma(-t, m.qd, x);
-    r = r < 0.0 ? r + m.qd : r;
-    r = r >= m.qd ? r - m.qd : r;
-    return r;
+// Nearest integer of x for |x| < 2^51: adding and removing 1.5 * 2^52 leaves
+// no fraction bits (round to nearest even).  Written as an fma so the product
+// x * s is not rounded before the shift.
+__device__ __forceinline__ double round_mul(double x, double s) {
+    constexpr double SHIFT = 6755399441055744.0;   // 1.5 * 2^52
+    return fma(x, s, SHIFT) - SHIFT;
 }
 
 // Recombines the seven digit-product classes of one output,
 //   sum_s G_s 2^(8s) mod q,   |G_s| <= 2^27,
-// entirely in exact binary64 arithmetic:
-//   E = G_0 + 2^8 G_1 + 2^16 G_2 + 2^24 G_3       |E| < 2^52 (exact)
-//   H = G_4 + 2^8 G_5 + 2^16 G_6                  |H| < 2^44 (exact)
-//   h = H mod q = 2^15 h1 + h0 (h0, h1 < 2^15)
-//   result = E + h0 (2^32 mod q) + h1 (2^47 mod q)   mod q
-// where each product stays below 2^45, so the sum is exact before reduction.
-// (M is any struct with qd, qinv, c32, c47.)
-template <class M>
+// in exact binary64 arithmetic:
+//   E = G_0 + 2^8 G_1 + 2^16 G_2 + 2^24 G_3        |E| < 2^51 + 2^44 (exact)
+//   H = G_4 + 2^8 G_5 + 2^16 G_6                   |H| < 2^44 (exact)
+//   h = H - round(H/q) q                           |h| < q (exact remainder)
+// then, with c32 = 2^32 mod q,
+//   SPLIT = false:  t = E + h c32, exact when q c32 < 3 * 2^51 - 2^45 (the
+//                   host checks this; it holds for every q < 2^26 and for q
+//                   just below 2^30, where c32 = 4 (2^30 - q) is small);
+//   SPLIT = true:   h = 2^15 h1 + h0 (0 <= h0 < 2^15, |h1| <= 2^15) and
+//                   t = E + h0 c32 + h1 c47, c47 = 2^47 mod q, each product
+//                   below 2^45 in magnitude;
+// finally r = t - round(t/q) q lies in (-q, q) and min(r, r + q) taken as
+// unsigned 32-bit words is the canonical residue.  (M is any struct with
+// qd, qinv, c32, c47 and q.)
+template <bool SPLIT, class M>
 __device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const M &m) {
     double e = (double)g[3];
     e = fma(e, 256.0, (double)g[2]);
@@ -90,12 +91,24 @@ __device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const M &
     double hh = (double)g[6];
     hh = fma(hh, 256.0, (double)g[5]);
     hh = fma(hh, 256.0, (double)g[4]);
-    const double h = fp_reduce(hh, m);
-    const double h1 = floor(h * (1.0 / 32768.0));
-    const double h0 = fma(-h1, 32768.0, h);
-    double t = fma(h0, m.c32, e);
-    t = fma(h1, m.c47, t);
-    return (uint32_t)fp_reduce(t, m);
+    const double h = fma(-round_mul(hh, m.qinv), m.qd, hh);
+    double t;
+    if (SPLIT) {
+        const double h1 = floor(h * (1.0 / 32768.0));
+        const double h0 = fma(-h1, 32768.0, h);
+        t = fma(h0, m.c32, e);
+        t = fma(h1, m.c47, t);
+    } else {
+        t = fma(h, m.c32, e);
+    }
+    const uint32_t r = (uint32_t)(int32_t)fma(-round_mul(t, m.qinv), m.qd, t);
+    return min(r, r + m.q);
+}
+
+// Whether the SPLIT = false recombination is exact for q (see above).
+__host__ __device__ inline bool combine_direct_ok(uint32_t q) {
+    const double c32 = (double)((1ull << 32) % q);
+    return (double)q * c32 <= 3.0 * 2251799813685248.0 - 35184372088832.0;   // 3*2^51 - 2^45
 }
 
 // Balanced signed base-2^8 digits of x < 2^31: x = sum_i d_i 2^(8i),

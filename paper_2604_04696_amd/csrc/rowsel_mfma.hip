@@ -22,8 +22,10 @@
 #include <list>
 #include <mutex>
 #include <vector>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #include "common.h"
 #include "modarith.h"
@@ -41,42 +43,44 @@ struct ModQ4m {
 // ----------------------------------------------------------- digit planes
 // Generic transpose + digit split:  element (r, k, p) of a uint32 source at
 // src[r*s_r + (k - klo)*s_k + p] (points p contiguous) goes to byte k%64 of
-// row r of chunk k/64 of plane [p][d]: dst[(((p*4 + d)*Kp/64 + k/64)*R + r)*64 + k%64].  A block takes one row r,
-// 64 k (aligned) and 64 points: it reads 64 runs of 256 bytes, splits in
-// LDS, and writes 64-byte runs.  k outside [klo, khi) and rows r >= r_valid
-// read as zero; 16-byte chunks that straddle [klo, khi) (only when loading
-// a DB in row ranges) are written byte by byte so neighbouring ranges are
-// not overwritten.
+// row r of chunk k/64 of plane [p][d]:
+//   dst[(((p*4 + d)*Kp/64 + k/64)*RS + row0 + r)*64 + k%64].
+// A block takes two rows r, r+1, 64 k (aligned) and 64 points: it reads 128
+// runs of 256 bytes, splits in LDS, and writes one 128-byte run (the two
+// rows' 64-byte chunk rows, adjacent in dst) per point and digit.  k outside
+// [klo, khi) and rows r >= r_valid read as zero; rows r >= R are not
+// written; 16-byte chunks that straddle [klo, khi) (only when loading a DB
+// in row ranges) are written byte by byte so neighbouring ranges are not
+// overwritten.
 __global__ void __launch_bounds__(256)
 digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k,
                     int8_t *__restrict__ dst, uint32_t R, uint32_t r_valid, uint32_t P,
                     uint32_t kp, uint32_t klo, uint32_t khi, uint32_t kvalid, uint32_t kblk0,
                     uint32_t nkblk, uint32_t RS, uint32_t row0) {
-    __shared__ uint32_t tile[64][65];
+    __shared__ uint32_t tile[2][64][65];
     const uint32_t tid = threadIdx.x;
     uint64_t b = blockIdx.x;
     const uint32_t npb = (P + 63) / 64;
     const uint32_t pb = (uint32_t)(b % npb);
     b /= npb;
     const uint32_t kb = kblk0 + (uint32_t)(b % nkblk);
-    const uint32_t r = (uint32_t)(b / nkblk);
+    const uint32_t r0 = 2 * (uint32_t)(b / nkblk);
     const uint32_t k0 = kb * 64, p0 = pb * 64;
-    const bool rv = r < r_valid;
 
-    for (uint32_t e = tid; e < 64 * 64; e += 256) {
-        uint32_t kk = e / 64, pp = e % 64;
-        uint32_t k = k0 + kk;
+    for (uint32_t e = tid; e < 2 * 64 * 64; e += 256) {
+        const uint32_t rr = e / 4096, kk = (e / 64) % 64, pp = e % 64;
+        const uint32_t k = k0 + kk, r = r0 + rr;
         uint32_t v = 0;
-        if (rv && k >= klo && k < khi && p0 + pp < P)
+        if (r < r_valid && k >= klo && k < khi && p0 + pp < P)
             v = split_digits(src[(uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp]);
-        tile[kk][pp] = v;
+        tile[rr][kk][pp] = v;
     }
     __syncthreads();
 
-    for (uint32_t c = tid; c < 1024; c += 256) {
-        const uint32_t kq = c % 4, d = (c / 4) % 4, pp = c / 16;
-        const uint32_t kc = k0 + kq * 16;
-        if (kc >= kp || p0 + pp >= P) continue;
+    for (uint32_t c = tid; c < 2048; c += 256) {
+        const uint32_t kq = c % 4, rr = (c / 4) % 2, d = (c / 8) % 4, pp = c / 32;
+        const uint32_t kc = k0 + kq * 16, r = r0 + rr;
+        if (r >= R || kc >= kp || p0 + pp >= P) continue;
         const uint32_t hv = std::min(kc + 16, kvalid);   // k >= kvalid is padding
         const bool inside = kc >= klo && hv <= khi;
         uint32_t w[4];
@@ -85,7 +89,7 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
             uint32_t x = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                x |= ((tile[kq * 16 + i4 * 4 + i][pp] >> (8 * d)) & 0xFFu) << (8 * i);
+                x |= ((tile[rr][kq * 16 + i4 * 4 + i][pp] >> (8 * d)) & 0xFFu) << (8 * i);
             w[i4] = x;
         }
         int8_t *o = dst + ((((uint64_t)(p0 + pp) * 4 + d) * (kp / 64) + kc / 64) * RS + row0 + r) * 64 + kc % 64;
@@ -110,7 +114,7 @@ static void launch_digit_planes(const uint32_t *src, uint64_t s_r, uint64_t s_k,
     // the padding up to Kp (Kp is D0 rounded up to 64)
     const uint32_t kb0 = klo / 64, kb1 = (khi + 63) / 64;
     const uint32_t nkb = kb1 - kb0;
-    const uint64_t blocks = (uint64_t)((P + 63) / 64) * nkb * R;
+    const uint64_t blocks = (uint64_t)((P + 63) / 64) * nkb * ((R + 1) / 2);
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "digit-plane launch too large");
     digit_planes_kernel<<<(uint32_t)blocks, 256, 0, st>>>(src, s_r, s_k, dst, R, r_valid, P, kp, klo,
                                                           khi, kvalid, kb0, nkb, RS, row0);
@@ -296,7 +300,7 @@ struct LoadCursor {
 //
 // A single instance travels by value in `one` (ONE = true); a grouped launch
 // passes a device array of jobs sorted by tile0.
-template <bool ONE, int BM>
+template <bool ONE, int BM, bool SPLIT>
 __global__ void __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint32_t njobs,
                        uint32_t total_tiles) {
@@ -368,7 +372,7 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
     i32x16 acc[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
-    uint32_t res[4][16];
+    uint32_t res[16];   // this point's result (summed over K chunks of KSUPER rows)
 
     uint32_t outstanding = 0;   // steps issued beyond the one being computed
     for (int k = 0; k < NSTAGE - 1 && !l_done; ++k) {
@@ -394,20 +398,37 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
         if (active) {
             const int8_t *buf = lds + cbuf * STAGE_BYTES;
             const int8_t *abuf = buf + abase, *bbuf = buf + bbase;
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                i32x4 a[4];
+            // Fragments go to distinct registers and are read ahead of their
+            // use: k-step 0's eight, then (after its first MFMA group) k-step
+            // 1's eight, which overlap k-step 0's remaining MFMAs.  At most
+            // eleven reads are outstanding, within the LDS wait counter's
+            // range, so each group waits only for its own fragments.  The
+            // scheduling barriers keep the compiler from sinking the reads
+            // back to their uses and keep the MFMAs in groups of four
+            // distinct classes (no back-to-back accumulator dependence).
+            i32x4 a[2][4], b[2][4];
+            auto read_frags = [&](int ks) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d)
-                    a[d] = *reinterpret_cast<const i32x4 *>(abuf + d * a_stride + achunk[ks]);
+                    a[ks][d] = *reinterpret_cast<const i32x4 *>(abuf + d * a_stride + achunk[ks]);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const i32x4 b = *reinterpret_cast<const i32x4 *>(bbuf + j * b_stride + bchunk[ks]);
+                for (int d = 0; d < 4; ++d)
+                    b[ks][d] = *reinterpret_cast<const i32x4 *>(bbuf + d * b_stride + bchunk[ks]);
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            auto mfma_group = [&](int ks, int j) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b, acc[i + j], 0, 0, 0);
-                }
-            }
+                for (int i = 0; i < 4; ++i)
+                    acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ks][i], b[ks][j], acc[i + j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            read_frags(0);
+            mfma_group(0, 0);
+            read_frags(1);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) mfma_group(0, j);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mfma_group(1, j);
         }
         cbuf = cbuf + 1 == NSTAGE ? 0 : cbuf + 1;
         const bool last = kc + 1 == ct.nkc;
@@ -415,42 +436,36 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
             // recombine the seven classes of this point: sum_s G_s 2^(8s) mod q
             const EpiQ mq = ONE ? one.q[ct.l] : jobs[ct.job].q[ct.l];
             const bool first = kc + 1 <= KSUPER / KCH;
-            uint32_t part[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int gr[7];
 #pragma unroll
                 for (int c = 0; c < 7; ++c) gr[c] = acc[c][r];
-                part[r] = combine_classes(gr, mq);
-            }
-#pragma unroll
-            for (int ss = 0; ss < 4; ++ss) {
-                if ((uint32_t)ss != s) continue;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) res[ss][r] = first ? part[r] : add_mod(res[ss][r], part[r], mq.q);
+                const uint32_t part = combine_classes<SPLIT>(gr, mq);
+                res[r] = first ? part : add_mod(res[r], part, mq.q);
             }
 #pragma unroll
             for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
+            if (last) {
+                // the point is done: its rows go to the staging layout
+                // [point][mp][d1]; accumulator element r of a lane is row
+                // 8*(r/4) + 4*(lane/32) + r%4, column lane%32 of the wave's
+                // 32 x 32 sub-tile, so each store moves two 128-byte runs
+                const uint32_t n = ct.n0 + wni * 32 + lane % 32;
+                if (active && n < ct.d1) {
+                    uint32_t *pt = ct.out + (uint64_t)(4 * ct.gl + s) * ct.mp * ct.d1 + n;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t m = ct.m0 + wmi * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                        pt[(uint64_t)m * ct.d1] = res[r];
+                    }
+                }
+                after_store = true;
+            }
         }
         if (++kc == ct.nkc) {
             kc = 0;
             if (++s == 4) {
-                // the tile's four points are done: one 16-byte vector per
-                // (m, n) into the staging layout [group][mp][d1][4], where the
-                // 32 lanes of a row write 512 contiguous bytes.  Accumulator
-                // element r of a lane is row 8*(r/4) + 4*(lane/32) + r%4,
-                // column lane%32 of the wave's 32 x 32 sub-tile.
-                const uint32_t n = ct.n0 + wni * 32 + lane % 32;
-                if (active && n < ct.d1) {
-                    uint32_t *grp = ct.out + (uint64_t)ct.gl * ct.mp * ct.d1 * 4;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const uint32_t m = ct.m0 + wmi * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                        *reinterpret_cast<uint4 *>(grp + ((uint64_t)m * ct.d1 + n) * 4) =
-                            make_uint4(res[0][r], res[1][r], res[2][r], res[3][r]);
-                    }
-                }
-                after_store = true;
                 s = 0;
                 ++ci;
                 c_done = tile_index(ci) >= total_tiles;
@@ -464,45 +479,41 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
     }
 }
 
-// Output transpose: staging [G_all][mp][d1][4] (G_all = L*N/4 point groups)
-// -> boundary layout [B][2][d1][L][N].  A block takes one row m, 32 columns
-// and 32 consecutive groups (128 points): it reads 32 runs of 512 bytes
-// (one per group) and writes 32 runs of 512 bytes (one per column), so both
-// sides move whole cache lines (the paper's output transposition of
-// sec. 5.2.2, here a separate coalesced pass instead of 16-byte scatter).
+// Output transpose: staging [P][mp][d1] (P = L*N points) -> boundary layout
+// [B][2][d1][L][N], i.e. for every row m < m_rows a P x d1 -> d1 x P
+// transpose.  A block takes one row m, 64 points and 64 columns: it reads 64
+// runs of 256 bytes (columns contiguous) and writes 64 runs of 256 bytes
+// (points contiguous), through a padded LDS tile (the paper's output
+// transposition of sec. 5.2.2, here one coalesced pass).
 __global__ void __launch_bounds__(256)
-out_transpose_kernel(const uint4 *__restrict__ stage, uint4 *__restrict__ out, uint32_t m_rows,
-                     uint32_t mp, uint32_t d1, uint32_t gall, uint32_t nblk_n, uint32_t nblk_g) {
-    __shared__ uint4 tile[32][33];   // [column][group]
+out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ out, uint32_t mp, uint32_t d1,
+                     uint32_t P, uint32_t nblk_n, uint32_t nblk_p) {
+    __shared__ uint32_t tile[64][65];   // [column][point]
     const uint32_t tid = threadIdx.x;
     uint32_t b = blockIdx.x;
-    const uint32_t gb = b % nblk_g;
-    b /= nblk_g;
+    const uint32_t pb = b % nblk_p;
+    b /= nblk_p;
     const uint32_t nb = b % nblk_n;
     const uint32_t m = b / nblk_n;
-    const uint32_t g0 = gb * 32, n0 = nb * 32;
-    for (uint32_t e = tid; e < 1024; e += 256) {
-        const uint32_t gi = e / 32, ni = e % 32;
-        if (g0 + gi < gall && n0 + ni < d1)
-            tile[ni][gi] = stage[((uint64_t)(g0 + gi) * mp + m) * d1 + n0 + ni];
+    const uint32_t p0 = pb * 64, n0 = nb * 64;
+    for (uint32_t e = tid; e < 4096; e += 256) {
+        const uint32_t pi = e / 64, ni = e % 64;
+        if (p0 + pi < P && n0 + ni < d1) tile[ni][pi] = stage[((uint64_t)(p0 + pi) * mp + m) * d1 + n0 + ni];
     }
     __syncthreads();
-    for (uint32_t e = tid; e < 1024; e += 256) {
-        const uint32_t ni = e / 32, gi = e % 32;
-        if (g0 + gi < gall && n0 + ni < d1) out[((uint64_t)m * d1 + n0 + ni) * gall + g0 + gi] = tile[ni][gi];
+    for (uint32_t e = tid; e < 4096; e += 256) {
+        const uint32_t ni = e / 64, pi = e % 64;
+        if (p0 + pi < P && n0 + ni < d1) out[((uint64_t)m * d1 + n0 + ni) * P + p0 + pi] = tile[ni][pi];
     }
 }
 
 void launch_out_transpose(const uint32_t *stage, uint32_t *out, uint32_t m_rows, uint32_t mp, uint32_t d1,
                           uint32_t slots, hipStream_t st) {
-    const uint32_t gall = slots / 4;
-    const uint32_t nblk_n = (d1 + 31) / 32, nblk_g = (gall + 31) / 32;
-    const uint64_t blocks = (uint64_t)m_rows * nblk_n * nblk_g;
+    const uint32_t nblk_n = (d1 + 63) / 64, nblk_p = (slots + 63) / 64;
+    const uint64_t blocks = (uint64_t)m_rows * nblk_n * nblk_p;
     if (!blocks) return;
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "transpose launch too large");
-    out_transpose_kernel<<<(uint32_t)blocks, 256, 0, st>>>(reinterpret_cast<const uint4 *>(stage),
-                                                           reinterpret_cast<uint4 *>(out), m_rows, mp, d1,
-                                                           gall, nblk_n, nblk_g);
+    out_transpose_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, out, mp, d1, slots, nblk_n, nblk_p);
     PIR_LAUNCH_CHECK();
 }
 
@@ -538,9 +549,11 @@ MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_
     j.nblk_n = (p.d1 + 32 * (NWAVE / wm) - 1) / (32 * (NWAVE / wm));
     j.tile0 = tile0;
     j.tiles = j.groups * j.nblk_m * j.nblk_n;
+    j.split = 0;
     for (uint32_t l = 0; l < p.nprimes; ++l) {
         const ModQ &m = db.mod[l];
         j.q[l] = EpiQ{m.qd, m.qinv, m.c32, m.c47, m.q, 0};
+        if (!combine_direct_ok(m.q)) j.split = 1;
     }
     return j;
 }
@@ -560,13 +573,24 @@ void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njob
                       hipStream_t st) {
     if (!total_tiles) return;
     const uint32_t grid = 8 * (uint32_t)std::max(1, cu_count() / 8);
-    // every job of one launch shares the tile shape of `one`
+    // every job of one launch shares the tile shape and the recombination
+    // variant of `one`
+    auto go = [&](auto bm, auto split) {
+        constexpr int BM = decltype(bm)::value;
+        constexpr bool SPLIT = decltype(split)::value;
+        if (jobs_dev)
+            rowsel_mfma_persistent<false, BM, SPLIT><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
+        else
+            rowsel_mfma_persistent<true, BM, SPLIT><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+    };
+    using B64 = std::integral_constant<int, 64>;
+    using B128 = std::integral_constant<int, 128>;
     if (one.wm == 4) {
-        if (jobs_dev) rowsel_mfma_persistent<false, 128><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
-        else rowsel_mfma_persistent<true, 128><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+        if (one.split) go(B128{}, std::true_type{});
+        else go(B128{}, std::false_type{});
     } else {
-        if (jobs_dev) rowsel_mfma_persistent<false, 64><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
-        else rowsel_mfma_persistent<true, 64><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+        if (one.split) go(B64{}, std::true_type{});
+        else go(B64{}, std::false_type{});
     }
     PIR_LAUNCH_CHECK();
 }
@@ -589,7 +613,7 @@ void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st) {
     // scratch: query digit planes [P][4][Kp/64][Mp][64], then the output
-    // staging [P/4][Mp][D1][4]
+    // staging [P][Mp][D1]
     const uint32_t mp = (2 * B + 31) / 32 * 32;
     const size_t qbytes = (mfma_query_scratch_bytes(db, B) + 255) / 256 * 256;
     const size_t sbytes = (size_t)db.slots() * mp * db.p.d1 * 4;
@@ -630,12 +654,9 @@ static std::mutex g_plan_mu;
 static std::list<GroupPlan> g_plans;   // most recently used first
 constexpr size_t MAX_PLANS = 8;
 
-uint32_t pick_group_wm(const pir_rowsel_item *items, uint32_t count) {
-    if (const char *e = std::getenv("PIR_MFMA_WM")) {
-        const int v = std::atoi(e);
-        if (v == 2 || v == 4) return (uint32_t)v;
-    }
-    // the shape that wastes fewer padded rows over the whole group
+// Tile shape that pads fewer rows over the whole group (the choice when
+// timing is switched off with PIR_AUTOTUNE=0).
+static uint32_t pick_group_wm(const pir_rowsel_item *items, uint32_t count) {
     uint64_t waste4 = 0, waste2 = 0;
     for (uint32_t i = 0; i < count; ++i) {
         if (!items[i].B) continue;
@@ -649,27 +670,41 @@ uint32_t pick_group_wm(const pir_rowsel_item *items, uint32_t count) {
     return waste4 <= waste2 ? 4u : 2u;
 }
 
-static GroupPlan &get_plan(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
-    std::vector<std::pair<const pir_db *, uint32_t>> key(count);
-    for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
-    const uint32_t wm = pick_group_wm(items, count);
-    int dev = 0;
-    PIR_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(g_plan_mu);
+// PIR_MFMA_WM=4 or 2 forces the 128 x 64 or the 64 x 128 tile (0: not forced).
+static uint32_t forced_wm() {
+    if (const char *e = std::getenv("PIR_MFMA_WM")) {
+        const int v = std::atoi(e);
+        if (v == 2 || v == 4) return (uint32_t)v;
+    }
+    return 0;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        PIR_HIP(hipEventCreate(&a));
+        PIR_HIP(hipEventCreate(&b));
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+static GroupPlan *find_plan(const std::vector<std::pair<const pir_db *, uint32_t>> &key, int dev, uint32_t forced) {
     for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
-        if (it->key == key && it->wm == wm && it->device == dev) {
+        if (it->key == key && it->device == dev && (!forced || it->wm == forced)) {
             g_plans.splice(g_plans.begin(), g_plans, it);
-            return g_plans.front();
+            return &g_plans.front();
         }
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    PIR_HIP(hipStreamIsCapturing(st, &cap));
-    PIR_REQUIRE(cap == hipStreamCaptureStatusNone,
-                "pir_rowsel_grouped: the first call for a set of item shapes allocates and cannot be captured");
-    g_plans.emplace_front();
-    GroupPlan &pl = g_plans.front();
-    pl.key = key;
-    pl.device = dev;
-    pl.wm = wm;
+    return nullptr;
+}
+
+// Builds the plan of a new item set.  Unless a shape is forced (or timing is
+// off), both tile shapes run once on the call's own inputs, timed with events
+// on the call's stream, and the faster one is kept for every later call.
+static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t count, uint32_t forced,
+                       hipStream_t st) {
     // layout of the scratch: per job [query digits][staging], then the job table
     std::vector<size_t> qoff, soff;
     size_t bytes = 0;
@@ -689,24 +724,107 @@ static GroupPlan &get_plan(const pir_rowsel_item *items, uint32_t count, hipStre
     const size_t jobs_off = bytes;
     bytes += sizeof(MfmaJob) * count + 256;
     pl.scratch = static_cast<int8_t *>(dev_alloc(bytes));
-    uint32_t tile0 = 0;
-    for (uint32_t i = 0; i < count; ++i) {
-        if (!items[i].B) {
-            pl.item_job.push_back(SIZE_MAX);
-            continue;
-        }
-        pl.item_job.push_back(pl.jobs.size());
-        MfmaJob j = make_mfma_job(*items[i].db, pl.scratch + qoff[i],
-                                  reinterpret_cast<uint32_t *>(pl.scratch + soff[i]), items[i].B, tile0, wm);
-        tile0 += j.tiles;
-        pl.jobs.push_back(j);
-    }
-    pl.total_tiles = tile0;
     pl.jobs_dev = reinterpret_cast<MfmaJob *>(pl.scratch + jobs_off);
-    if (!pl.jobs.empty())
-        PIR_HIP(hipMemcpy(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(), hipMemcpyHostToDevice));
+
+    auto set_shape = [&](uint32_t wm) {
+        pl.wm = wm;
+        pl.jobs.clear();
+        pl.item_job.clear();
+        uint32_t tile0 = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            if (!items[i].B) {
+                pl.item_job.push_back(SIZE_MAX);
+                continue;
+            }
+            pl.item_job.push_back(pl.jobs.size());
+            MfmaJob j = make_mfma_job(*items[i].db, pl.scratch + qoff[i],
+                                      reinterpret_cast<uint32_t *>(pl.scratch + soff[i]), items[i].B, tile0, wm);
+            tile0 += j.tiles;
+            pl.jobs.push_back(j);
+        }
+        pl.total_tiles = tile0;
+        // one recombination variant per launch: the split one if any job needs it
+        uint32_t split = 0;
+        for (const MfmaJob &j : pl.jobs) split |= j.split;
+        for (MfmaJob &j : pl.jobs) j.split = split;
+        if (!pl.jobs.empty()) {
+            PIR_HIP(hipMemcpyAsync(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(),
+                                   hipMemcpyHostToDevice, st));
+            PIR_HIP(hipStreamSynchronize(st));
+        }
+    };
+
+    uint32_t wm = forced;
+    if (!wm) {
+        const char *tune = std::getenv("PIR_AUTOTUNE");
+        if (tune && std::strcmp(tune, "0") == 0) wm = pick_group_wm(items, count);
+    }
+    if (!wm) {
+        set_shape(4);
+        if (pl.jobs.empty()) return;
+        // the query digit planes do not depend on the tile shape
+        for (uint32_t i = 0; i < count; ++i)
+            if (pl.item_job[i] != SIZE_MAX)
+                launch_query_digits(*items[i].db, items[i].q_dev, items[i].B,
+                                    const_cast<int8_t *>(pl.jobs[pl.item_job[i]].qd), st);
+        EventPair ev;
+        float best = 0.0f;
+        for (uint32_t cand : {4u, 2u}) {
+            if (cand != pl.wm) set_shape(cand);
+            for (int rep = 0; rep < 2; ++rep) {
+                PIR_HIP(hipEventRecord(ev.a, st));
+                launch_mfma_jobs(pl.jobs[0], pl.jobs_dev, (uint32_t)pl.jobs.size(), pl.total_tiles, st);
+                PIR_HIP(hipEventRecord(ev.b, st));
+                PIR_HIP(hipEventSynchronize(ev.b));
+                float ms = 0.0f;
+                PIR_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                if (!wm || ms < best) {
+                    best = ms;
+                    wm = cand;
+                }
+            }
+        }
+    }
+    if (wm != pl.wm || pl.jobs.empty()) set_shape(wm);
+}
+
+static GroupPlan &get_plan(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
+    std::vector<std::pair<const pir_db *, uint32_t>> key(count);
+    for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
+    const uint32_t forced = forced_wm();
+    int dev = 0;
+    PIR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    if (GroupPlan *pl = find_plan(key, dev, forced)) return *pl;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    PIR_HIP(hipStreamIsCapturing(st, &cap));
+    PIR_REQUIRE(cap == hipStreamCaptureStatusNone,
+                "pir_rowsel_grouped: the first call for a set of item shapes allocates and cannot be captured");
+    g_plans.emplace_front();
+    GroupPlan &pl = g_plans.front();
+    pl.key = key;
+    pl.device = dev;
+    try {
+        build_plan(pl, items, count, forced, st);
+    } catch (...) {
+        g_plans.pop_front();   // frees what was allocated
+        throw;
+    }
     while (g_plans.size() > MAX_PLANS) g_plans.pop_back();
     return g_plans.front();
+}
+
+bool group_plan_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *bm, uint32_t *bn) {
+    std::vector<std::pair<const pir_db *, uint32_t>> key(count);
+    for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
+    int dev = 0;
+    PIR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    GroupPlan *pl = find_plan(key, dev, 0);
+    if (!pl) return false;
+    *bm = 32 * pl->wm;
+    *bn = 32 * (NWAVE / pl->wm);
+    return true;
 }
 
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {

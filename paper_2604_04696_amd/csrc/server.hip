@@ -21,32 +21,33 @@
 
 namespace pir {
 
-// Staging [cg][mp][d1][4] of one step -> per-row destinations.  Row m holds
-// slot m/2, component m%2; row_dst[m] is that component's [D1][L*N/4] array
-// of 16-byte vectors (0 = discard).  A block takes one row, 32 columns and
-// 32 point groups and moves 512-byte runs on both sides.
+// Staging [cp][mp][d1] of one step (cp points, starting at point p_begin of
+// the DB) -> per-row destinations.  Row m holds slot m/2, component m%2;
+// row_dst[m] is that component's [D1][L*N] array (0 = discard).  A block
+// takes one row, 64 columns and 64 points and moves 256-byte runs on both
+// sides through a padded LDS tile.
 __global__ void __launch_bounds__(256)
-serve_scatter_kernel(const uint4 *__restrict__ stage, const uint64_t *__restrict__ row_dst, uint32_t mp,
-                     uint32_t d1, uint32_t cg, uint32_t g_begin, uint32_t gall, uint32_t nblk_n,
-                     uint32_t nblk_g) {
-    __shared__ uint4 tile[32][33];
+serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restrict__ row_dst, uint32_t mp,
+                     uint32_t d1, uint32_t cp, uint32_t p_begin, uint32_t pall, uint32_t nblk_n,
+                     uint32_t nblk_p) {
+    __shared__ uint32_t tile[64][65];   // [column][point]
     const uint32_t tid = threadIdx.x;
     uint32_t b = blockIdx.x;
-    const uint32_t gb = b % nblk_g;
-    b /= nblk_g;
+    const uint32_t pb = b % nblk_p;
+    b /= nblk_p;
     const uint32_t nb = b % nblk_n;
     const uint32_t m = b / nblk_n;
-    uint4 *dst = reinterpret_cast<uint4 *>(row_dst[m]);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(row_dst[m]);
     if (!dst) return;   // uniform for the block
-    const uint32_t g0 = gb * 32, n0 = nb * 32;
-    for (uint32_t e = tid; e < 1024; e += 256) {
-        const uint32_t gi = e / 32, ni = e % 32;
-        if (g0 + gi < cg && n0 + ni < d1) tile[ni][gi] = stage[((uint64_t)(g0 + gi) * mp + m) * d1 + n0 + ni];
+    const uint32_t p0 = pb * 64, n0 = nb * 64;
+    for (uint32_t e = tid; e < 4096; e += 256) {
+        const uint32_t pi = e / 64, ni = e % 64;
+        if (p0 + pi < cp && n0 + ni < d1) tile[ni][pi] = stage[((uint64_t)(p0 + pi) * mp + m) * d1 + n0 + ni];
     }
     __syncthreads();
-    for (uint32_t e = tid; e < 1024; e += 256) {
-        const uint32_t ni = e / 32, gi = e % 32;
-        if (g0 + gi < cg && n0 + ni < d1) dst[(uint64_t)(n0 + ni) * gall + g_begin + g0 + gi] = tile[ni][gi];
+    for (uint32_t e = tid; e < 4096; e += 256) {
+        const uint32_t ni = e / 64, pi = e % 64;
+        if (p0 + pi < cp && n0 + ni < d1) dst[(uint64_t)(n0 + ni) * pall + p_begin + p0 + pi] = tile[ni][pi];
     }
 }
 
@@ -199,10 +200,11 @@ struct pir_server {
         job.groups = ng;
         job.tiles = ng * job.nblk_m * job.nblk_n;
         launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
-        const uint32_t nblk_n = (db->p.d1 + 31) / 32, nblk_g = (ng + 31) / 32;
-        const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_g;
-        serve_scatter_kernel<<<(uint32_t)blocks, 256, 0, st>>>(reinterpret_cast<const uint4 *>(stage), row_dst_dev,
-                                                               job.mp, db->p.d1, ng, g_begin, gall, nblk_n, nblk_g);
+        const uint32_t cp = 4 * ng, nblk_n = (db->p.d1 + 63) / 64, nblk_p = (cp + 63) / 64;
+        const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_p;
+        PIR_REQUIRE(blocks < (1ull << 31), "scatter launch too large");
+        serve_scatter_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, row_dst_dev, job.mp, db->p.d1, cp,
+                                                               4 * g_begin, 4 * gall, nblk_n, nblk_p);
         PIR_LAUNCH_CHECK();
         Step step;
         for (uint32_t s = 0; s < capacity; ++s) {

@@ -97,6 +97,10 @@ def test_null_arguments(L):
     assert L.pir_db_load_ntt(None, None, 0, 1, 0, None) == pir.PIR_EINVAL
     assert L.pir_db_create(None, 1, None) == pir.PIR_EINVAL
     L.pir_db_free(None)   # no-op
+    tm, tn = ctypes.c_uint32(), ctypes.c_uint32()
+    assert L.pir_rowsel_grouped_tile(None, 0, None, None) == pir.PIR_EINVAL
+    assert L.pir_rowsel_grouped_tile(None, 1, ctypes.byref(tm), ctypes.byref(tn)) == pir.PIR_EINVAL
+    assert "NULL" in pir.pir_last_error()
 
 
 def test_ntt_helper_rejects_bad_modulus(L):

@@ -80,6 +80,29 @@ def test_grouped_graph_replay(pir):
                 assert np.array_equal(got, want), f"replay {rep} differs"
 
 
+def test_grouped_tile_choice(pir, monkeypatch):
+    """The plan keeps a tile shape, timed or forced, and any shape gives the
+    same bits."""
+    items, wants = _small_items(pir)
+    with pytest.raises(pir.PirError, match="no grouped plan"):
+        pir.pir_rowsel_grouped_tile(items[:3])
+    outs = {}
+    for forced in ("", "4", "2"):
+        monkeypatch.setenv("PIR_MFMA_WM", forced)
+        for _, _, B, out in items:
+            out.fill_(0)
+        pir.pir_rowsel_grouped(items[:3], pir.PIR_PATH_MFMA_I8)
+        torch.cuda.synchronize()
+        tm, tn = pir.pir_rowsel_grouped_tile(items[:3])
+        assert (tm, tn) in ((128, 64), (64, 128))
+        if forced:
+            assert tm == 32 * int(forced)
+        for (db, q, B, out), want in zip(items[:3], wants[:3]):
+            if B:
+                assert np.array_equal(np_u32(out)[: want.size].reshape(want.shape), want), forced
+    monkeypatch.delenv("PIR_MFMA_WM")
+
+
 def test_grouped_first_call_refuses_capture(pir):
     items, _ = _small_items(pir)
     items = items[:2]

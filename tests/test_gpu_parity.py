@@ -84,6 +84,12 @@ SHAPES = [
     (128, synth.PRIMES_N4096, 31, 40, 33),
     (64, synth.PRIMES_N4096, 1, 1, 1),
     (16, synth.PRIMES_N4096, 200, 5, 64),
+    # D0 above the 2048-row int32 accumulation chunk of the MFMA path
+    (16, synth.PRIMES_N4096, 4200, 5, 2),
+    # a prime with large 2^32 mod q (954376193: the recombination takes the
+    # split form), alone and beside a prime that does not need it
+    (64, (954376193,), 600, 24, 3),
+    (64, (954376193, 1073692673), 130, 40, 17),
 ]
 
 
@@ -122,23 +128,27 @@ def test_rowsel_ntt_domain_load_and_row_chunks(pir, path):
     assert np.array_equal(np_u32(out).reshape(want.shape), want)
 
 
+@pytest.mark.parametrize("case", [(32, synth.PRIMES_N4096, 1000, 40), (16, (954376193,), 4100, 8)],
+                         ids=["two_primes_1000", "split_prime_4100"])
 @BOTH
-def test_rowsel_all_q_minus_one(pir, path):
+def test_rowsel_all_q_minus_one(pir, path, case):
     # (q-1)^2 = 1 mod q: every output is D0 mod q; stresses the lazy 64-bit
     # bound and the largest digit products
-    n, primes, d0, d1, B = 32, synth.PRIMES_N4096, 1000, 40, 2
-    say("q-1 path", path)
-    dhat = np.empty((d0, d1, 2, n), dtype=np.uint32)
-    qv = np.empty((B, 2, d0, 2, n), dtype=np.uint32)
+    n, primes, d0, d1 = case
+    B = 2
+    say("q-1 path", path, case)
+    dhat = np.empty((d0, d1, len(primes), n), dtype=np.uint32)
+    qv = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
     for l, q in enumerate(primes):
         dhat[..., l, :] = q - 1
         qv[..., l, :] = q - 1
     db = pir.pir_db_create(pir.make_params(n, primes, d0, d1))
     pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
-    out = empty_u32(B * 2 * d1 * 2 * n)
+    out = empty_u32(B * 2 * d1 * len(primes) * n)
     pir.pir_rowsel(db, to_dev(qv), out, path)
     torch.cuda.synchronize()
-    assert np.all(np_u32(out) == d0)
+    want = np.array([d0 % q for q in primes], dtype=np.uint32)
+    assert np.all(np_u32(out).reshape(B, 2, d1, len(primes), n) == want[:, None])
 
 
 # ------------------------------------------------------- toy encryption
