@@ -16,13 +16,14 @@ struct EpiQ {
 struct MfmaJob {
     const int8_t *qd;      // query digit planes [L*N][4][nkc][mstride][64]
     const int8_t *dbd;     // DB digit planes    [L*N][4][nkc][d1][64]
-    uint32_t *out;         // staging [points][mp][d1] (see out_transpose_kernel)
+    uint32_t *out;         // staging [points][mp][sstride] (see out_transpose_kernel)
     uint32_t m_rows, mp, d1, nkc, L, N;
     uint32_t mstride;      // rows of a query plane (>= mp)
     uint32_t g_begin;      // first point group (groups of four points) of this job
     uint32_t wm;           // waves along m: 4 (128 x 64 tiles) or 2 (64 x 128 tiles)
     uint32_t nblk_m, nblk_n, groups, tile0, tiles;
     uint32_t split;        // 1: some prime needs the split recombination (combine_classes)
+    uint32_t sstride;      // staging row stride: d1 rounded up to a multiple of 4 (16-byte rows)
     EpiQ q[PIR_MAX_PRIMES];
 };
 
@@ -32,6 +33,9 @@ MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_
 uint32_t pick_wm(uint32_t B);
 void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
                       hipStream_t st);
+// Staging row stride of a DB with d1 columns (16-byte aligned rows).
+inline uint32_t staging_stride(uint32_t d1) { return (d1 + 3) / 4 * 4; }
+
 void launch_query_digits(const pir_db &db, const uint32_t *q, uint32_t B, int8_t *qd, hipStream_t st);
 void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows, int8_t *qd,
                               uint32_t mstride, uint32_t row0, hipStream_t st);

@@ -67,17 +67,26 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
     const uint32_t r0 = 2 * (uint32_t)(b / nkblk);
     const uint32_t k0 = kb * 64, p0 = pb * 64;
 
-    for (uint32_t e = tid; e < 2 * 64 * 64; e += 256) {
-        const uint32_t rr = e / 4096, kk = (e / 64) % 64, pp = e % 64;
+    // all 32 loads of a thread are issued before the first LDS store
+    uint32_t v[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t e = tid + 256 * j, rr = e / 4096, kk = (e / 64) % 64, pp = e % 64;
         const uint32_t k = k0 + kk, r = r0 + rr;
-        uint32_t v = 0;
-        if (r < r_valid && k >= klo && k < khi && p0 + pp < P)
-            v = split_digits(src[(uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp]);
-        tile[rr][kk][pp] = v;
+        v[j] = r < r_valid && k >= klo && k < khi && p0 + pp < P
+                   ? src[(uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp]
+                   : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t e = tid + 256 * j;
+        tile[e / 4096][(e / 64) % 64][e % 64] = split_digits(v[j]);
     }
     __syncthreads();
 
-    for (uint32_t c = tid; c < 2048; c += 256) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t c = tid + 256 * j;
         const uint32_t kq = c % 4, rr = (c / 4) % 2, d = (c / 8) % 4, pp = c / 32;
         const uint32_t kc = k0 + kq * 16, r = r0 + rr;
         if (r >= R || kc >= kp || p0 + pp >= P) continue;
@@ -173,27 +182,19 @@ __device__ __forceinline__ void block_barrier() { asm volatile("s_barrier" ::: "
 struct Tile {
     const int8_t *qd, *dbd;
     uint32_t *out;
-    uint32_t m_rows, mp, mstride, d1, nkc, L, N, bm, bn, wn, l, g, m0, n0, job, gl;
+    uint32_t m_rows, mp, mstride, d1, sstride, nkc, L, N, bm, bn, wn, l, g, m0, n0, job, gl;
 };
 
-// Global tile index -> tile.  Within a job, eight consecutive point groups
-// (32 points: the points one output line holds per (m, n)) are numbered
-// together for each (m, n) block, and the blocks of one octet follow each
-// other, so concurrently processed tiles share query planes and output lines.
+// Global tile index -> tile.  Within a job the (m, n) blocks of one point
+// group are numbered consecutively, so the tiles that run at the same time
+// on one XCD share that group's query digit planes in its L2.
 __device__ __forceinline__ Tile decode_tile(uint32_t T, const MfmaJob &J, uint32_t j) {
     const uint32_t loc = T - J.tile0;
-    const uint32_t tiles = J.nblk_m * J.nblk_n, per_oct = 8 * tiles, full = J.groups / 8;
-    uint32_t gg, tile;
-    if (loc < full * per_oct) {
-        gg = (loc / per_oct) * 8 + loc % 8;
-        tile = (loc % per_oct) / 8;
-    } else {
-        const uint32_t rem = loc - full * per_oct, w = J.groups - full * 8;
-        gg = full * 8 + rem % w;
-        tile = rem / w;
-    }
+    const uint32_t tiles = J.nblk_m * J.nblk_n;
+    uint32_t gg = loc / tiles;
+    const uint32_t tile = loc % tiles;
     Tile t;
-    t.gl = gg;            // group index inside the job (staging row block)
+    t.gl = gg;            // group index inside the job (staging points 4*gl .. 4*gl+3)
     gg += J.g_begin;
     t.qd = J.qd;
     t.dbd = J.dbd;
@@ -202,6 +203,7 @@ __device__ __forceinline__ Tile decode_tile(uint32_t T, const MfmaJob &J, uint32
     t.mp = J.mp;
     t.mstride = J.mstride;
     t.d1 = J.d1;
+    t.sstride = J.sstride;
     t.nkc = J.nkc;
     t.L = J.L;
     t.N = J.N;
@@ -448,16 +450,16 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
             for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
             if (last) {
                 // the point is done: its rows go to the staging layout
-                // [point][mp][d1]; accumulator element r of a lane is row
+                // [point][mp][sstride]; accumulator element r of a lane is row
                 // 8*(r/4) + 4*(lane/32) + r%4, column lane%32 of the wave's
                 // 32 x 32 sub-tile, so each store moves two 128-byte runs
                 const uint32_t n = ct.n0 + wni * 32 + lane % 32;
                 if (active && n < ct.d1) {
-                    uint32_t *pt = ct.out + (uint64_t)(4 * ct.gl + s) * ct.mp * ct.d1 + n;
+                    uint32_t *pt = ct.out + (uint64_t)(4 * ct.gl + s) * ct.mp * ct.sstride + n;
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const uint32_t m = ct.m0 + wmi * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                        pt[(uint64_t)m * ct.d1] = res[r];
+                        pt[(uint64_t)m * ct.sstride] = res[r];
                     }
                 }
                 after_store = true;
@@ -479,16 +481,17 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
     }
 }
 
-// Output transpose: staging [P][mp][d1] (P = L*N points) -> boundary layout
-// [B][2][d1][L][N], i.e. for every row m < m_rows a P x d1 -> d1 x P
-// transpose.  A block takes one row m, 64 points and 64 columns: it reads 64
-// runs of 256 bytes (columns contiguous) and writes 64 runs of 256 bytes
-// (points contiguous), through a padded LDS tile (the paper's output
-// transposition of sec. 5.2.2, here one coalesced pass).
+// Output transpose: staging [P][mp][ss] (P = L*N points, ss = d1 rounded up
+// to a multiple of 4) -> boundary layout [B][2][d1][L][N], i.e. for every row
+// m < m_rows a P x d1 -> d1 x P transpose.  A block takes one row m, 64
+// points and 64 columns: it reads 64 runs of 256 bytes (columns contiguous)
+// and writes 64 runs of 256 bytes (points contiguous), 16-byte vectors on
+// both sides through a padded LDS tile (the paper's output transposition of
+// sec. 5.2.2, here one coalesced pass).  P is a multiple of 4 (N >= 4).
 __global__ void __launch_bounds__(256)
 out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ out, uint32_t mp, uint32_t d1,
-                     uint32_t P, uint32_t nblk_n, uint32_t nblk_p) {
-    __shared__ uint32_t tile[64][65];   // [column][point]
+                     uint32_t ss, uint32_t P, uint32_t nblk_n, uint32_t nblk_p) {
+    __shared__ __attribute__((aligned(16))) uint32_t tile[64][68];   // [column][point]
     const uint32_t tid = threadIdx.x;
     uint32_t b = blockIdx.x;
     const uint32_t pb = b % nblk_p;
@@ -496,14 +499,29 @@ out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ 
     const uint32_t nb = b % nblk_n;
     const uint32_t m = b / nblk_n;
     const uint32_t p0 = pb * 64, n0 = nb * 64;
-    for (uint32_t e = tid; e < 4096; e += 256) {
-        const uint32_t pi = e / 64, ni = e % 64;
-        if (p0 + pi < P && n0 + ni < d1) tile[ni][pi] = stage[((uint64_t)(p0 + pi) * mp + m) * d1 + n0 + ni];
+    uint4 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+        v[j] = p0 + pi < P && n0 + 4 * nq < d1
+                   ? *reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq)
+                   : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+        tile[4 * nq + 0][pi] = v[j].x;
+        tile[4 * nq + 1][pi] = v[j].y;
+        tile[4 * nq + 2][pi] = v[j].z;
+        tile[4 * nq + 3][pi] = v[j].w;
     }
     __syncthreads();
-    for (uint32_t e = tid; e < 4096; e += 256) {
-        const uint32_t ni = e / 64, pi = e % 64;
-        if (p0 + pi < P && n0 + ni < d1) out[((uint64_t)m * d1 + n0 + ni) * P + p0 + pi] = tile[ni][pi];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = tid + 256 * j, ni = e / 16, pq = e % 16;
+        if (n0 + ni < d1 && p0 + 4 * pq < P)
+            *reinterpret_cast<uint4 *>(out + ((uint64_t)m * d1 + n0 + ni) * P + p0 + 4 * pq) =
+                *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]);
     }
 }
 
@@ -513,7 +531,8 @@ void launch_out_transpose(const uint32_t *stage, uint32_t *out, uint32_t m_rows,
     const uint64_t blocks = (uint64_t)m_rows * nblk_n * nblk_p;
     if (!blocks) return;
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "transpose launch too large");
-    out_transpose_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, out, mp, d1, slots, nblk_n, nblk_p);
+    out_transpose_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, out, mp, d1, staging_stride(d1), slots, nblk_n,
+                                                           nblk_p);
     PIR_LAUNCH_CHECK();
 }
 
@@ -540,6 +559,7 @@ MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_
     j.mstride = j.mp;
     j.g_begin = 0;
     j.d1 = p.d1;
+    j.sstride = staging_stride(p.d1);
     j.nkc = db.mfma.kp / KCH;
     j.L = p.nprimes;
     j.N = p.n;
@@ -613,10 +633,10 @@ void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st) {
     // scratch: query digit planes [P][4][Kp/64][Mp][64], then the output
-    // staging [P][Mp][D1]
+    // staging [P][Mp][sstride]
     const uint32_t mp = (2 * B + 31) / 32 * 32;
     const size_t qbytes = (mfma_query_scratch_bytes(db, B) + 255) / 256 * 256;
-    const size_t sbytes = (size_t)db.slots() * mp * db.p.d1 * 4;
+    const size_t sbytes = (size_t)db.slots() * mp * staging_stride(db.p.d1) * 4;
     int8_t *scratch = nullptr;
     PIR_HIP(hipMallocAsync((void **)&scratch, qbytes + sbytes, st));
     uint32_t *stage = reinterpret_cast<uint32_t *>(scratch + qbytes);
@@ -719,7 +739,7 @@ static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t cou
         qoff.push_back(bytes);
         bytes += (mfma_query_scratch_bytes(db, items[i].B) + 255) / 256 * 256;
         soff.push_back(bytes);
-        bytes += ((size_t)db.slots() * mp * db.p.d1 * 4 + 255) / 256 * 256;
+        bytes += ((size_t)db.slots() * mp * staging_stride(db.p.d1) * 4 + 255) / 256 * 256;
     }
     const size_t jobs_off = bytes;
     bytes += sizeof(MfmaJob) * count + 256;

@@ -21,16 +21,17 @@
 
 namespace pir {
 
-// Staging [cp][mp][d1] of one step (cp points, starting at point p_begin of
-// the DB) -> per-row destinations.  Row m holds slot m/2, component m%2;
-// row_dst[m] is that component's [D1][L*N] array (0 = discard).  A block
-// takes one row, 64 columns and 64 points and moves 256-byte runs on both
-// sides through a padded LDS tile.
+// Staging [cp][mp][ss] of one step (cp points, starting at point p_begin of
+// the DB; ss = d1 rounded up to a multiple of 4) -> per-row destinations.
+// Row m holds slot m/2, component m%2; row_dst[m] is that component's
+// [D1][L*N] array (0 = discard).  A block takes one row, 64 columns and 64
+// points and moves 256-byte runs of 16-byte vectors on both sides through a
+// padded LDS tile (cp, p_begin and pall are multiples of 4).
 __global__ void __launch_bounds__(256)
 serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restrict__ row_dst, uint32_t mp,
-                     uint32_t d1, uint32_t cp, uint32_t p_begin, uint32_t pall, uint32_t nblk_n,
+                     uint32_t d1, uint32_t ss, uint32_t cp, uint32_t p_begin, uint32_t pall, uint32_t nblk_n,
                      uint32_t nblk_p) {
-    __shared__ uint32_t tile[64][65];   // [column][point]
+    __shared__ __attribute__((aligned(16))) uint32_t tile[64][68];   // [column][point]
     const uint32_t tid = threadIdx.x;
     uint32_t b = blockIdx.x;
     const uint32_t pb = b % nblk_p;
@@ -40,14 +41,29 @@ serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restr
     uint32_t *dst = reinterpret_cast<uint32_t *>(row_dst[m]);
     if (!dst) return;   // uniform for the block
     const uint32_t p0 = pb * 64, n0 = nb * 64;
-    for (uint32_t e = tid; e < 4096; e += 256) {
-        const uint32_t pi = e / 64, ni = e % 64;
-        if (p0 + pi < cp && n0 + ni < d1) tile[ni][pi] = stage[((uint64_t)(p0 + pi) * mp + m) * d1 + n0 + ni];
+    uint4 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+        v[j] = p0 + pi < cp && n0 + 4 * nq < d1
+                   ? *reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq)
+                   : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+        tile[4 * nq + 0][pi] = v[j].x;
+        tile[4 * nq + 1][pi] = v[j].y;
+        tile[4 * nq + 2][pi] = v[j].z;
+        tile[4 * nq + 3][pi] = v[j].w;
     }
     __syncthreads();
-    for (uint32_t e = tid; e < 4096; e += 256) {
-        const uint32_t ni = e / 64, pi = e % 64;
-        if (p0 + pi < cp && n0 + ni < d1) dst[(uint64_t)(n0 + ni) * pall + p_begin + p0 + pi] = tile[ni][pi];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = tid + 256 * j, ni = e / 16, pq = e % 16;
+        if (n0 + ni < d1 && p0 + 4 * pq < cp)
+            *reinterpret_cast<uint4 *>(dst + (uint64_t)(n0 + ni) * pall + p_begin + p0 + 4 * pq) =
+                *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]);
     }
 }
 
@@ -123,7 +139,7 @@ struct pir_server {
     // device bytes for `cap` client slots
     uint64_t bytes_for(uint32_t cap) const {
         const uint64_t P = db->slots(), ms = (2ull * cap + 127) / 128 * 128;
-        return P * 4 * db->mfma.kp * ms + (uint64_t)cg * ms * db->p.d1 * 16 + ms * 8 + 4096;
+        return P * 4 * db->mfma.kp * ms + (uint64_t)cg * ms * staging_stride(db->p.d1) * 16 + ms * 8 + 4096;
     }
 
     void flush_rows() {
@@ -203,8 +219,8 @@ struct pir_server {
         const uint32_t cp = 4 * ng, nblk_n = (db->p.d1 + 63) / 64, nblk_p = (cp + 63) / 64;
         const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_p;
         PIR_REQUIRE(blocks < (1ull << 31), "scatter launch too large");
-        serve_scatter_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, row_dst_dev, job.mp, db->p.d1, cp,
-                                                               4 * g_begin, 4 * gall, nblk_n, nblk_p);
+        serve_scatter_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, row_dst_dev, job.mp, db->p.d1, job.sstride,
+                                                               cp, 4 * g_begin, 4 * gall, nblk_n, nblk_p);
         PIR_LAUNCH_CHECK();
         Step step;
         for (uint32_t s = 0; s < capacity; ++s) {
@@ -270,7 +286,8 @@ pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_
             srv->mstride = (2 * cap + 127) / 128 * 128;
             const uint64_t P = db->slots();
             srv->qd = static_cast<int8_t *>(dev_alloc(P * 4 * db->mfma.kp * srv->mstride));
-            srv->stage = static_cast<uint32_t *>(dev_alloc((uint64_t)srv->cg * srv->mstride * db->p.d1 * 16));
+            srv->stage = static_cast<uint32_t *>(
+                dev_alloc((uint64_t)srv->cg * srv->mstride * staging_stride(db->p.d1) * 16));
             srv->row_dst_dev = static_cast<uint64_t *>(dev_alloc((uint64_t)srv->mstride * 8));
             srv->device_bytes = srv->bytes_for(cap);
             // every row starts as "discard"; query rows start zeroed
