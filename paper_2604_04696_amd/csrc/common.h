@@ -102,14 +102,30 @@ const NttTables &ntt_tables(uint32_t q, uint32_t n);
 
 // ------------------------------------------------------------------ the DB
 struct DbLayoutValu {
-    // [L][N/4][D0][D1][4] uint32: for a group of four consecutive NTT points
-    // of one prime, each DB row is a contiguous run of D1 16-byte vectors.
+    // [L][N/4][S][D0][W][4] uint32: for a group of four consecutive NTT
+    // points of one prime, the D1 columns are cut into S strips of
+    // VALU_STRIP columns (the last one narrower, W = its width), and the D0
+    // rows of one strip are one contiguous run of D0*W 16-byte vectors.
     uint32_t *data = nullptr;
 };
 
+constexpr uint32_t VALU_STRIP = 256;
+
+// Offset (in 16-byte vectors) of strip `strip` of point group gg, and the
+// strip's width; element (row k, column n) of the strip is at
+// valu_strip_base(...) + k * width + (n % VALU_STRIP).
+__host__ __device__ inline uint64_t valu_strip_base(uint64_t gg, uint32_t strip, uint32_t d0, uint32_t d1) {
+    return gg * d0 * d1 + (uint64_t)strip * VALU_STRIP * d0;
+}
+__host__ __device__ inline uint32_t valu_strip_width(uint32_t strip, uint32_t d1) {
+    const uint32_t left = d1 - strip * VALU_STRIP;
+    return left < VALU_STRIP ? left : VALU_STRIP;
+}
+
 struct DbLayoutMfma {
-    // [L*N][4][D1][Kp] int8: per point p and digit d, column n holds the
-    // d-th signed 8-bit digit of DB[k][n] for k < D0, zero for D0 <= k < Kp.
+    // [L*N][4][Kp/64][D1][64] int8: per point p and digit d, chunk c of
+    // column n holds the d-th signed 8-bit digits of DB[64c .. 64c+63][n]
+    // (zero for D0 <= k < Kp).
     int8_t *data = nullptr;
     uint32_t kp = 0;   // D0 rounded up to a multiple of 64
 };

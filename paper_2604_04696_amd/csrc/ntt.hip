@@ -172,7 +172,8 @@ void launch_ntt(const uint32_t *in, uint32_t *out, uint64_t count, uint64_t in_s
 }
 
 // ------------------------------------------------------------ DB layouts
-// NTT-domain source rows [nrows][D1][L][N] -> VALU layout [L][N/4][D0][D1][4].
+// NTT-domain source rows [nrows][D1][L][N] -> VALU layout [L][N/4][S][D0][W][4]
+// (256-column strips, see DbLayoutValu).
 // One thread moves one 16-byte vector (four consecutive points); consecutive
 // threads take consecutive columns so every store wavefront is one
 // contiguous 1 KiB run.
@@ -190,8 +191,10 @@ __global__ void db_layout_valu_kernel(const uint32_t *__restrict__ src, uint32_t
         uint32_t l = (uint32_t)(r2 % L);
         uint32_t r = (uint32_t)(r2 / L);
         const uint4 v = *reinterpret_cast<const uint4 *>(src + (((uint64_t)r * d1 + n) * L + l) * N + 4 * g);
-        uint64_t o = ((((uint64_t)l * G + g) * d0 + (row0 + r)) * d1 + n) * 4;
-        *reinterpret_cast<uint4 *>(dst + o) = v;
+        const uint32_t strip = n / VALU_STRIP;
+        const uint64_t o = valu_strip_base((uint64_t)l * G + g, strip, d0, d1) +
+                           (uint64_t)(row0 + r) * valu_strip_width(strip, d1) + n % VALU_STRIP;
+        *reinterpret_cast<uint4 *>(dst + 4 * o) = v;
     }
 }
 

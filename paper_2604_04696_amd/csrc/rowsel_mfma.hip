@@ -221,69 +221,74 @@ __device__ __forceinline__ Tile decode_tile(uint32_t T, const MfmaJob &J, uint32
 
 // Load side of the pipeline for one wave and tile shape BM x BN: which
 // operand, digit plane and 16-row block each of the wave's LPW load
-// instructions covers is fixed by (wave, instruction); everything that
-// depends on the tile is computed when a tile starts, and a step costs a few
-// 64-bit scalar adds per load.  Byte offset of (point s, digit d, chunk kc,
+// instructions covers is fixed by (wave, instruction).  The first QL
+// instructions of every wave read query planes, the rest DB planes (A_INST
+// is a multiple of NWAVE), so the per-step advance of each instruction's
+// address is a compile-time choice between two plane sizes.  Each lane keeps
+// the full 64-bit address of each of its loads, set when a tile starts and
+// advanced by one add per step.  Byte offset of (point s, digit d, chunk kc,
 // row r) in a plane set: ((s*4 + d)*nkc + kc)*plane + r*64, plane = rows*64.
 template <int BM>
 struct LoadCursor {
     static constexpr int BN = ROWS - BM;
     static constexpr int A_INST = 4 * BM / 16;   // query instructions (16 rows each)
-    const int8_t *qbase, *dbase;                 // planes of the tile's first point
-    uint64_t qstep, dstep, qplane, dplane;       // current (s, kc) offset, plane bytes
-    uint64_t doff[LPW];                          // d * nkc * plane per instruction
-    uint32_t loff[LPW];                          // per lane: clamped row * 64 + swizzled chunk
+    static constexpr int QL = A_INST / NWAVE;     // query loads of each wave
+    static_assert(A_INST % NWAVE == 0, "query loads must split evenly among the waves");
+    const int8_t *src[LPW];                       // per lane: address of each load's next step
+    uint64_t qplane, dplane;                      // bytes of one query / DB plane chunk
+    uint32_t lds[LPW];                            // LDS offset of each load inside a stage
     uint32_t kc, s, nkc;
 
-    static __device__ __forceinline__ bool is_q(int i, uint32_t wv) { return wv + i * NWAVE < (uint32_t)A_INST; }
+    // LDS destination of instruction i inside a stage
+    static __device__ __forceinline__ uint32_t lds_off(int i, uint32_t wv) {
+        const uint32_t ii = wv + i * NWAVE;
+        if (i < QL) return (ii / (BM / 16)) * BM * KCH + (ii % (BM / 16)) * 1024;
+        const uint32_t jj = ii - A_INST;
+        return 4 * BM * KCH + (jj / (BN / 16)) * BN * KCH + (jj % (BN / 16)) * 1024;
+    }
+
+    __device__ __forceinline__ void init(uint32_t wv) {
+#pragma unroll
+        for (int i = 0; i < LPW; ++i) lds[i] = lds_off(i, wv);
+    }
 
     __device__ __forceinline__ void start(const Tile &t, uint32_t wv, uint32_t lane) {
         const uint64_t p0 = (uint64_t)t.l * t.N + 4 * t.g;
         qplane = (uint64_t)t.mstride * KCH;
         dplane = (uint64_t)t.d1 * KCH;
-        qbase = t.qd + p0 * 4 * t.nkc * qplane;
-        dbase = t.dbd + p0 * 4 * t.nkc * dplane;
-        qstep = dstep = 0;
+        const int8_t *qbase = t.qd + p0 * 4 * t.nkc * qplane;
+        const int8_t *dbase = t.dbd + p0 * 4 * t.nkc * dplane;
         kc = s = 0;
         nkc = t.nkc;
         const uint32_t lrow = lane / 4, lchunk = lane % 4;
 #pragma unroll
         for (int i = 0; i < LPW; ++i) {
             const uint32_t ii = wv + i * NWAVE;
-            const bool q = ii < (uint32_t)A_INST;
+            const bool q = i < QL;
             const uint32_t jj = q ? ii : ii - A_INST, rbn = q ? BM / 16 : BN / 16;
             const uint32_t d = jj / rbn, rb = jj % rbn, r = rb * 16 + lrow;
-            doff[i] = (uint64_t)d * t.nkc * (q ? qplane : dplane);
-            loff[i] = q ? min(t.m0 + r, t.mp - 1) * KCH : min(t.n0 + r, t.d1 - 1) * KCH;
-            loff[i] += 16 * (lchunk ^ swz(r));
+            uint32_t off = q ? min(t.m0 + r, t.mp - 1) * KCH : min(t.n0 + r, t.d1 - 1) * KCH;
+            off += 16 * (lchunk ^ swz(r));
+            src[i] = (q ? qbase + (uint64_t)d * t.nkc * qplane : dbase + (uint64_t)d * t.nkc * dplane) + off;
         }
-    }
-
-    // LDS destination of instruction i inside a stage
-    static __device__ __forceinline__ uint32_t lds_off(int i, uint32_t wv) {
-        const uint32_t ii = wv + i * NWAVE;
-        if (ii < (uint32_t)A_INST) return (ii / (BM / 16)) * BM * KCH + (ii % (BM / 16)) * 1024;
-        const uint32_t jj = ii - A_INST;
-        return 4 * BM * KCH + (jj / (BN / 16)) * BN * KCH + (jj % (BN / 16)) * 1024;
     }
 
     // Issues this wave's loads of the current step into `stage`; returns
     // true when the tile's last step has been issued.
-    __device__ __forceinline__ bool issue(int8_t *stage, uint32_t wv) {
+    __device__ __forceinline__ bool issue(int8_t *stage) {
 #pragma unroll
         for (int i = 0; i < LPW; ++i) {
             // (a named pointer: an arithmetic expression as the builtin's
             // argument stops the host pass from emitting the kernel stub)
-            const int8_t *src = (is_q(i, wv) ? qbase + qstep : dbase + dstep) + doff[i] + loff[i];
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(stage + lds_off(i, wv)),
-                                             16, 0, 0);
+            const int8_t *from = src[i];
+            __builtin_amdgcn_global_load_lds(from, (__attribute__((address_space(3))) void *)(stage + lds[i]), 16,
+                                             0, 0);
+            src[i] += i < QL ? qplane : dplane;
         }
-        qstep += qplane;
-        dstep += dplane;
         if (++kc == nkc) {
             kc = 0;
-            qstep += 3ull * nkc * qplane;
-            dstep += 3ull * nkc * dplane;
+#pragma unroll
+            for (int i = 0; i < LPW; ++i) src[i] += 3ull * nkc * (i < QL ? qplane : dplane);
             if (++s == 4) return true;
         }
         return false;
@@ -326,13 +331,14 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
     bool l_done = tile_index(0) >= total_tiles;
     Tile lt{};
     LoadCursor<BM> lc;
+    lc.init(wv);
     if (!l_done) {
         lt = decode(tile_index(0));
         lc.start(lt, wv, lane);
     }
     uint32_t lbuf = 0;   // stage of the next issue
     auto issue_next = [&]() {
-        const bool tile_end = lc.issue(lds + lbuf * STAGE_BYTES, wv);
+        const bool tile_end = lc.issue(lds + lbuf * STAGE_BYTES);
         lbuf = lbuf + 1 == NSTAGE ? 0 : lbuf + 1;
         if (tile_end) {
             ++li;
@@ -392,40 +398,43 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
         else wait_vmcnt<0>();
         after_store = false;
         block_barrier();
+
+        // Fragments go to distinct registers and are read ahead of their
+        // use: k-step 0's eight, then (after its first MFMA group and this
+        // step's operand loads) k-step 1's eight, which overlap k-step 0's
+        // remaining MFMAs.  At most eleven reads are outstanding, within the
+        // LDS wait counter's range, so each group waits only for its own
+        // fragments.  The loads' address arithmetic is issued while the
+        // first group's MFMAs run.  The scheduling barriers keep the
+        // compiler from sinking the reads back to their uses and keep the
+        // MFMAs in groups of four distinct classes (no back-to-back
+        // accumulator dependence).
+        const int8_t *abuf = lds + cbuf * STAGE_BYTES + abase, *bbuf = lds + cbuf * STAGE_BYTES + bbase;
+        i32x4 a[2][4], b[2][4];
+        auto read_frags = [&](int ks) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                a[ks][d] = *reinterpret_cast<const i32x4 *>(abuf + d * a_stride + achunk[ks]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                b[ks][d] = *reinterpret_cast<const i32x4 *>(bbuf + d * b_stride + bchunk[ks]);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto mfma_group = [&](int ks, int j) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ks][i], b[ks][j], acc[i + j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        if (active) {
+            read_frags(0);
+            mfma_group(0, 0);
+        }
         if (!l_done) {
             issue_next();
             ++outstanding;
         }
-
         if (active) {
-            const int8_t *buf = lds + cbuf * STAGE_BYTES;
-            const int8_t *abuf = buf + abase, *bbuf = buf + bbase;
-            // Fragments go to distinct registers and are read ahead of their
-            // use: k-step 0's eight, then (after its first MFMA group) k-step
-            // 1's eight, which overlap k-step 0's remaining MFMAs.  At most
-            // eleven reads are outstanding, within the LDS wait counter's
-            // range, so each group waits only for its own fragments.  The
-            // scheduling barriers keep the compiler from sinking the reads
-            // back to their uses and keep the MFMAs in groups of four
-            // distinct classes (no back-to-back accumulator dependence).
-            i32x4 a[2][4], b[2][4];
-            auto read_frags = [&](int ks) {
-#pragma unroll
-                for (int d = 0; d < 4; ++d)
-                    a[ks][d] = *reinterpret_cast<const i32x4 *>(abuf + d * a_stride + achunk[ks]);
-#pragma unroll
-                for (int d = 0; d < 4; ++d)
-                    b[ks][d] = *reinterpret_cast<const i32x4 *>(bbuf + d * b_stride + bchunk[ks]);
-                __builtin_amdgcn_sched_barrier(0);
-            };
-            auto mfma_group = [&](int ks, int j) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ks][i], b[ks][j], acc[i + j], 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);
-            };
-            read_frags(0);
-            mfma_group(0, 0);
             read_frags(1);
 #pragma unroll
             for (int j = 1; j < 4; ++j) mfma_group(0, j);

@@ -3,12 +3,12 @@
 //
 // The operation (sec. 2.3): for each of the L*N points p and prime q_l,
 //   out[m][n] = sum_k Q[m][k] * DB[k][n] mod q_l.
-// Both kernels read the DB from the VALU layout [L][N/4][D0][D1][4]: a thread
-// owns four consecutive points of one prime (one 16-byte vector), so the
-// four independent per-point GEMMs of a group advance in lock step and each
-// DB row of a group is a contiguous run of D1 vectors (the transposed,
-// point-innermost layout that lets a wavefront stream whole rows; compare
-// the paper's transposed layout of sec. 5.2.1).  Queries and outputs are
+// Both kernels read the DB from the VALU layout [L][N/4][S][D0][W][4]: a
+// thread owns four consecutive points of one prime (one 16-byte vector), so
+// the four independent per-point GEMMs of a group advance in lock step, and
+// the D0 rows of a 256-column strip of a group are one contiguous run (the
+// transposed, point-innermost layout that lets a wavefront stream whole
+// rows; compare the paper's transposed layout of sec. 5.2.1).  Queries and outputs are
 // read/written in the boundary layout directly: for fixed (m, k) the points
 // are contiguous there as well, so a 16-byte vector per (m, k) / (m, n)
 // needs no separate transpose pass.
@@ -44,6 +44,7 @@ __device__ __forceinline__ void mad4(uint64_t (&acc)[4], const uint4 &a, const u
 // the HBM-bound regime of one client (sec. 3.1): two multiply-adds per
 // 4-byte DB word.
 constexpr int STREAM_THREADS = 256;
+static_assert(STREAM_THREADS == VALU_STRIP, "a streaming block covers one DB strip");
 constexpr int STREAM_UNROLL = 15;
 
 template <int MB>
@@ -61,7 +62,9 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
     const uint32_t n = nb * STREAM_THREADS + tid;
     if (n >= d1) return;
 
-    const uint4 *dcol = db + (uint64_t)gg * d0 * d1 + n;
+    // the block's columns are strip nb: its rows are one contiguous run
+    const uint32_t w = valu_strip_width(nb, d1);
+    const uint4 *dcol = db + valu_strip_base(gg, nb, d0, d1) + tid;
     // query vector (m, k) at qv + m*mstride + k*kstride (16-byte units)
     const uint4 *qv = reinterpret_cast<const uint4 *>(qry + (uint64_t)l * N + 4 * g);
     const uint64_t kstride = (uint64_t)L * N / 4, mstride = (uint64_t)d0 * kstride;
@@ -75,7 +78,7 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
     for (; k + STREAM_UNROLL <= d0; k += STREAM_UNROLL) {
         uint4 v[STREAM_UNROLL];
 #pragma unroll
-        for (int u = 0; u < STREAM_UNROLL; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * d1);
+        for (int u = 0; u < STREAM_UNROLL; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * w);
 #pragma unroll
         for (int u = 0; u < STREAM_UNROLL; ++u)
 #pragma unroll
@@ -87,7 +90,7 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
     }
     if (k < d0) {   // ragged tail: fewer than fifteen rows
         for (; k < d0; ++k) {
-            const uint4 v = ld_nt(dcol + (uint64_t)k * d1);
+            const uint4 v = ld_nt(dcol + (uint64_t)k * w);
 #pragma unroll
             for (int i = 0; i < MB; ++i) mad4(acc[i], qv[i * mstride + k * kstride], v);
         }
@@ -116,6 +119,7 @@ constexpr int TILE_THREADS = 256;
 constexpr int TM = 4, TN = 2;            // per-thread rows x columns
 constexpr int BM = 16 * TM, BN = 16 * TN;
 constexpr int TKC = 30;                   // rows per LDS step (two lazy groups)
+static_assert(VALU_STRIP % BN == 0, "a tiled block's columns lie in one DB strip");
 
 __global__ void __launch_bounds__(TILE_THREADS)
 rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
@@ -135,7 +139,9 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ q
     const uint32_t tm = tid / 16, tn = tid % 16;   // thread's rows tm + 16*i, cols tn + 16*j
     const uint32_t m0 = mb * BM, n0 = nb * BN;
 
-    const uint4 *dgrp = db + (uint64_t)gg * d0 * d1;
+    // the block's 32 columns lie in one strip (VALU_STRIP is a multiple of BN)
+    const uint32_t strip = n0 / VALU_STRIP, sw = valu_strip_width(strip, d1), c0 = n0 % VALU_STRIP;
+    const uint4 *dgrp = db + valu_strip_base(gg, strip, d0, d1) + c0;
     uint64_t acc[TM][TN][4];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -158,7 +164,7 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ q
         for (uint32_t e = tid; e < TKC * BN; e += TILE_THREADS) {
             uint32_t kk = e / BN, nn = e % BN;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (kk < kc && n0 + nn < d1) v = dgrp[(uint64_t)(k0 + kk) * d1 + n0 + nn];
+            if (kk < kc && n0 + nn < d1) v = dgrp[(uint64_t)(k0 + kk) * sw + nn];
             ds[kk][nn] = v;
         }
         __syncthreads();

@@ -167,11 +167,12 @@ def db_coeffs(seed: int, d0: int, d1: int, nprimes: int, n: int, sub: int = 0,
 
 
 def query_uniform(seed: int, b_count: int, d0: int, primes, n: int, sub: int = 0,
-                  clients=None) -> np.ndarray:
+                  clients=None, tag: int = TAG_QUERY) -> np.ndarray:
     """Uniform residues, layout [B][2][D0][L][N]; draw index is the flat index
     in the full [B][2][D0][L][N] array; limb l uses uniform_mod(., q_l).
-    ``clients`` selects client indices (default all); the result keeps their order."""
-    key = stream_key(seed, TAG_QUERY, sub)
+    ``clients`` selects client indices (default all); the result keeps their order.
+    ``tag`` names the stream (TAG_POOL for the serving workload's query pool)."""
+    key = stream_key(seed, tag, sub)
     L = len(primes)
     clients = np.arange(b_count) if clients is None else np.asarray(clients)
     per_client = 2 * d0 * L * n
