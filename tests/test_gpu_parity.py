@@ -84,6 +84,10 @@ SHAPES = [
     (128, synth.PRIMES_N4096, 31, 40, 33),
     (64, synth.PRIMES_N4096, 1, 1, 1),
     (16, synth.PRIMES_N4096, 200, 5, 64),
+    # D1 over three 256-column strips of the VALU layout (the last 8 wide),
+    # on the streaming (B <= 4) and the tiled (B > 4) VALU kernels
+    (16, synth.PRIMES_N4096, 33, 520, 2),
+    (16, synth.PRIMES_N4096, 70, 520, 9),
     # D0 above the 2048-row int32 accumulation chunk of the MFMA path
     (16, synth.PRIMES_N4096, 4200, 5, 2),
     # a prime with large 2^32 mod q (954376193: the recombination takes the

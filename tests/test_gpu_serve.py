@@ -121,3 +121,36 @@ def test_serve_budget_bounds_capacity(pir, served):
     pir.pir_server_destroy(small)
     with pytest.raises(pir.PirError, match="holds no client"):
         pir.pir_server_create(db, max_clients=4, hbm_budget=1024)
+
+
+def test_serve_full_size_sampled(pir):
+    """The serving workload's DB (N = 4096, two primes, 1024 x 1024, 32 GiB):
+    three requests from the seeded query pool, admitted while others run,
+    each checked against the oracle on two sampled DB columns."""
+    w = synth.SERVE_DB
+    print("building the 32 GiB serving DB", flush=True)
+    from helpers import device_db
+    db = device_db(pir, w.n, w.primes, w.d0, w.d1, w.seed, pir.PIR_LAYOUT_MFMA)
+    pool = []
+    for i in range(3):
+        q = empty_u32(2 * w.d0 * w.slots)
+        pir.pir_synth_query(q, synth.stream_key(w.seed, synth.TAG_POOL, i), 0, 1, w.d0, w.primes, w.n)
+        pool.append(q)
+    outs = [empty_u32(2 * w.d1 * w.slots) for _ in range(3)]
+    srv = pir.pir_server_create(db, max_clients=8, chunks=16)
+    print("serving", flush=True)
+    got = run_until(pir, srv, {0: [(0, pool[0], outs[0])], 2: [(1, pool[1], outs[1]), (2, pool[2], outs[2])]}, 3,
+                    timeout=120.0)
+    torch.cuda.synchronize()
+    pir.pir_server_destroy(srv)
+    cols = [3, w.d1 - 1]
+    coeffs = synth.db_coeffs(w.seed, w.d0, w.d1, 2, w.n, cols=cols)
+    dhat = oracle.ntt_db(coeffs, w.primes)
+    for i in range(3):
+        assert got[i].status == 0
+        # the pool query of request i, regenerated on the host from its seeded stream
+        qh = synth.query_uniform(w.seed, 1, w.d0, w.primes, w.n, sub=i, tag=synth.TAG_POOL)
+        want = oracle.rowsel(qh, dhat, w.primes)
+        out = np_u32(outs[i]).reshape(1, 2, w.d1, 2, w.n)[:, :, cols]
+        assert np.array_equal(out, want), f"request {i}"
+    pir.pir_db_free(db)
