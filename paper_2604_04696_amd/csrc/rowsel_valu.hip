@@ -110,6 +110,44 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------- query ingest
+// Larger batches read the query from a group-major copy
+//   qv[G_all][D0][Mp][4] u32   (G_all = L*N/4 point groups, Mp = rows rounded
+//                               up to the tile height, zero padded)
+// so that a tile's query rows for one k are one contiguous 1 KiB run and a
+// group's whole slice (D0 x Mp vectors) is contiguous and stays in L2 while
+// the group's column tiles run.  A block moves 8 groups x 16 k x 16 rows:
+// 128-byte reads (8 consecutive groups of one (row, k)) and 256-byte writes
+// (16 consecutive rows of one (group, k)) through a padded LDS tile.
+__global__ void __launch_bounds__(256)
+valu_query_kernel(const uint4 *__restrict__ q, uint4 *__restrict__ qv, uint32_t m_rows, uint32_t mp,
+                  uint32_t d0, uint32_t gall, uint32_t nkb, uint32_t ngb) {
+    // [group][k][row], group stride 273 vectors (not a multiple of the bank
+    // period) so the 8 groups a wave writes at once fall in distinct banks
+    __shared__ uint4 tile[8 * 273];
+    const uint32_t tid = threadIdx.x;
+    uint32_t b = blockIdx.x;
+    const uint32_t gb = b % ngb;
+    b /= ngb;
+    const uint32_t kb = b % nkb;
+    const uint32_t mb = b / nkb;
+    const uint32_t g0 = gb * 8, k0 = kb * 16, m0 = mb * 16;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t e = tid + 256 * j, gi = e % 8, ki = (e / 8) % 16, mi = e / 128;
+        const uint32_t g = g0 + gi, k = k0 + ki, m = m0 + mi;
+        tile[gi * 273 + ki * 17 + mi] = g < gall && k < d0 && m < m_rows ? q[((uint64_t)m * d0 + k) * gall + g]
+                                                                          : make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t e = tid + 256 * j, mi = e % 16, ki = (e / 16) % 16, gi = e / 256;
+        const uint32_t g = g0 + gi, k = k0 + ki;
+        if (g < gall && k < d0) qv[((uint64_t)g * d0 + k) * mp + m0 + mi] = tile[gi * 273 + ki * 17 + mi];
+    }
+}
+
 // ------------------------------------------------------------------ tiled
 // Larger batches: a 256-thread block computes a BM x BN output tile of one
 // point group (four points), thread tile TM x TN x 4 points, staging KC rows
@@ -122,8 +160,8 @@ constexpr int TKC = 30;                   // rows per LDS step (two lazy groups)
 static_assert(VALU_STRIP % BN == 0, "a tiled block's columns lie in one DB strip");
 
 __global__ void __launch_bounds__(TILE_THREADS)
-rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
-                    uint32_t *__restrict__ out, uint32_t m_rows, uint32_t d0, uint32_t d1,
+rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint4 *__restrict__ qv,
+                    uint32_t *__restrict__ out, uint32_t m_rows, uint32_t mp, uint32_t d0, uint32_t d1,
                     uint32_t L, uint32_t N, uint32_t nblk_m, uint32_t nblk_n, ModQ4 mods) {
     __shared__ uint4 qs[TKC][BM];
     __shared__ uint4 ds[TKC][BN];
@@ -142,6 +180,7 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ q
     // the block's 32 columns lie in one strip (VALU_STRIP is a multiple of BN)
     const uint32_t strip = n0 / VALU_STRIP, sw = valu_strip_width(strip, d1), c0 = n0 % VALU_STRIP;
     const uint4 *dgrp = db + valu_strip_base(gg, strip, d0, d1) + c0;
+    const uint4 *qgrp = qv + (uint64_t)gg * d0 * mp + m0;   // rows m0.. of this group, k-major
     uint64_t acc[TM][TN][4];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -156,9 +195,7 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ q
         for (uint32_t e = tid; e < TKC * BM; e += TILE_THREADS) {
             uint32_t kk = e / BM, mm = e % BM;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (kk < kc && m0 + mm < m_rows)
-                v = *reinterpret_cast<const uint4 *>(
-                    qry + (((uint64_t)(m0 + mm) * d0 + k0 + kk) * L + l) * N + 4 * g);
+            if (kk < kc) v = qgrp[(uint64_t)(k0 + kk) * mp + mm];   // rows >= m_rows are zero
             qs[kk][mm] = v;
         }
         for (uint32_t e = tid; e < TKC * BN; e += TILE_THREADS) {
@@ -243,10 +280,22 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
     } else {
         const uint32_t nblk_m = (m_rows + BM - 1) / BM;
         const uint32_t nblk_n = (p.d1 + BN - 1) / BN;
+        const uint32_t mp = nblk_m * BM;
         const uint64_t blocks = groups * nblk_m * nblk_n;
-        if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
+        const uint32_t nkb = (p.d0 + 15) / 16, ngb = (uint32_t)((groups + 7) / 8);
+        const uint64_t iblocks = (uint64_t)(mp / 16) * nkb * ngb;
+        if (blocks >= (1ull << 31) || iblocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
+        // stream-ordered scratch for the group-major query copy
+        uint4 *qv = nullptr;
+        PIR_HIP(hipMallocAsync((void **)&qv, groups * p.d0 * mp * sizeof(uint4), st));
+        valu_query_kernel<<<(uint32_t)iblocks, 256, 0, st>>>(reinterpret_cast<const uint4 *>(q), qv, m_rows, mp,
+                                                             p.d0, (uint32_t)groups, nkb, ngb);
+        PIR_LAUNCH_CHECK();
         rowsel_tiled_kernel<<<(uint32_t)blocks, TILE_THREADS, 0, st>>>(
-            dbv, q, out, m_rows, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
+            dbv, qv, out, m_rows, mp, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
+        PIR_LAUNCH_CHECK();
+        PIR_HIP(hipFreeAsync(qv, st));
+        return;
     }
     PIR_LAUNCH_CHECK();
 }
