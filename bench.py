@@ -77,17 +77,25 @@ def timed_calls(fn, reps):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "rowsel_stream_kernel_n4096_l2_512x512_b1.md")
-STREAM_SRC = os.path.join(ROOT, "paper_2604_04696_amd", "csrc", "rowsel_valu.hip")
+# the headline kernel and the headers it is compiled with
+STREAM_SRCS = [os.path.join(ROOT, "paper_2604_04696_amd", "csrc", f)
+               for f in ("rowsel_stream.hip", "modarith.h", "common.h")]
+
+
+def stream_source_sha256():
+    h = hashlib.sha256()
+    for f in STREAM_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the headline kernel from the committed counter
-    summary, or None when the kernel source changed since it was measured."""
+    summary, or None when the kernel's sources changed since it was measured."""
     try:
         text = open(PROFILE).read()
         rec = json.loads(text.split("<!-- traffic ")[1].split(" -->")[0])
-        sha = hashlib.sha256(open(STREAM_SRC, "rb").read()).hexdigest()
-        return rec["traffic_bytes"] if rec["source_sha256"] == sha else None
+        return rec["traffic_bytes"] if rec["source_sha256"] == stream_source_sha256() else None
     except (OSError, IndexError, KeyError, ValueError):
         return None
 
@@ -281,6 +289,18 @@ def main():
     db = build_db(pir, w, pir.PIR_LAYOUT_VALU | pir.PIR_LAYOUT_MFMA)
     log(f"DB built in {time.time() - t0:.1f} s")
 
+    # ------------------------------------------- measured HBM reference
+    # a STREAM-style pass on the same GPU: 2 GiB read + 2 GiB written
+    ref_src = torch.zeros(1 << 29, dtype=torch.int32, device="cuda")
+    ref_dst = torch.empty_like(ref_src)
+    for _ in range(2):
+        torch.bitwise_not(ref_src, out=ref_dst)
+    torch.cuda.synchronize()
+    ref_ms = statistics.median(timed_calls(lambda: torch.bitwise_not(ref_src, out=ref_dst), 10))
+    copy_gbs = 2 * ref_src.numel() * 4 / (ref_ms * 1e-3) / 1e9
+    del ref_src, ref_dst
+    torch.cuda.empty_cache()
+
     # ---------------------------------------------------------- headline
     q1 = make_query(pir, w, 1, w.seed)
     out1 = torch.empty(2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
@@ -326,7 +346,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "rowsel_stream_kernel<2>", "kernel_ms": round(kmean, 4),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "measured_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
     }
 
     # ------------------------------------------------------------ batched

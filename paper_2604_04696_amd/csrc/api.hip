@@ -163,7 +163,7 @@ void check_rowsel_args(const pir_db *db, const uint32_t *q, uint32_t B, const ui
 void rowsel_one(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, pir_path path,
                 hipStream_t st) {
     if (B == 0) return;
-    PIR_HIP(hipSetDevice(db.device));
+    DeviceGuard dg(db.device);
     if (env_flag("PIR_VALIDATE")) check_residues(q, (uint64_t)B * 2 * db.p.d0 * db.slots(), db.p, st);
     const pir_path use = resolve_path(db, B, path);
     if (use == PIR_PATH_VALU) launch_rowsel_valu(db, q, B, out, st);
@@ -227,9 +227,9 @@ uint32_t pir_db_layouts(const pir_db *db) { return db ? db->layouts : 0; }
 
 void pir_db_free(pir_db *db) {
     if (!db) return;
-    (void)hipSetDevice(db->device);
-    (void)hipDeviceSynchronize();
     try {
+        DeviceGuard dg(db->device);
+        (void)hipDeviceSynchronize();
         release_group_plans();
     } catch (...) {
     }
@@ -249,7 +249,7 @@ pir_status pir_db_load_ntt(pir_db *db, const uint32_t *src, uint32_t row0, uint3
         if (nrows == 0) return;
         PIR_REQUIRE(src != nullptr, "src is NULL");
         PIR_REQUIRE(reinterpret_cast<uintptr_t>(src) % 16 == 0, "src must be 16-byte aligned");
-        PIR_HIP(hipSetDevice(db->device));
+        DeviceGuard dg(db->device);
         hipStream_t st = as_stream(stream);
         const auto &p = db->p;
         const uint64_t poly = (uint64_t)p.nprimes * p.n;          // words per record

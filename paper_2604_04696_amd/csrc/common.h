@@ -159,6 +159,22 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Makes `dev` current for the guard's scope and restores the caller's
+// current device afterwards (entry points never leave it changed).
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) PIR_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
+};
+
 void *dev_alloc(size_t bytes);   // throws PIR_ENOMEM
 void dev_free(void *p);
 
@@ -174,6 +190,8 @@ void launch_db_layout_mfma(const pir_db &db, const uint32_t *ntt_src, uint32_t r
                            uint32_t nrows, hipStream_t st);
 void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st);
+void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
+                          hipStream_t st);   // 2B <= 8
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st);
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);

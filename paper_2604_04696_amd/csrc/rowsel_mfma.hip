@@ -672,9 +672,12 @@ struct GroupPlan {
     uint32_t total_tiles = 0;
     ~GroupPlan() {
         if (scratch) {
+            int prev = 0;
+            const bool had = hipGetDevice(&prev) == hipSuccess;
             (void)hipSetDevice(device);
             (void)hipDeviceSynchronize();
             dev_free(scratch);
+            if (had) (void)hipSetDevice(prev);
         }
     }
 };

@@ -1,17 +1,17 @@
-// RowSel on the vector ALUs: exact 32x32->64-bit multiply-adds (v_mad_u64_u32)
-// with lazy 64-bit accumulation.
+// RowSel on the vector ALUs for larger batches (2B > 8): exact 32x32->64-bit
+// multiply-adds (v_mad_u64_u32) with lazy 64-bit accumulation; one to four
+// clients take the streaming kernel of rowsel_stream.hip.
 //
 // The operation (sec. 2.3): for each of the L*N points p and prime q_l,
 //   out[m][n] = sum_k Q[m][k] * DB[k][n] mod q_l.
-// Both kernels read the DB from the VALU layout [L][N/4][S][D0][W][4]: a
+// The tiled kernel reads the DB from the VALU layout [L][N/4][S][D0][W][4]: a
 // thread owns four consecutive points of one prime (one 16-byte vector), so
 // the four independent per-point GEMMs of a group advance in lock step, and
 // the D0 rows of a 256-column strip of a group are one contiguous run (the
-// transposed, point-innermost layout that lets a wavefront stream whole
-// rows; compare the paper's transposed layout of sec. 5.2.1).  Queries and outputs are
-// read/written in the boundary layout directly: for fixed (m, k) the points
-// are contiguous there as well, so a 16-byte vector per (m, k) / (m, n)
-// needs no separate transpose pass.
+// transposed, point-innermost layout of the paper's sec. 5.2.1).  The query
+// is first copied into a group-major layout (valu_query_kernel); the output
+// is written in the boundary layout directly (for fixed (m, n) the four
+// points of a group are one 16-byte vector there).
 //
 // Accumulation: products of residues are < 2^60, so a 64-bit sum absorbs
 // fifteen of them on top of a folded remainder (< 2^60 + 2^32); every
@@ -33,81 +33,6 @@ __device__ __forceinline__ void mad4(uint64_t (&acc)[4], const uint4 &a, const u
     acc[1] += (uint64_t)a.y * b.y;
     acc[2] += (uint64_t)a.z * b.z;
     acc[3] += (uint64_t)a.w * b.w;
-}
-
-// --------------------------------------------------------------- streaming
-// Small batches (m = 2B <= 8 rows): the whole m extent lives in registers;
-// a block owns one point group and 256 consecutive columns and streams the
-// group's DB rows once.  The query vector of (m, k) is the same for every
-// lane, so it is read with scalar loads into SGPRs and feeds
-// v_mad_u64_u32 as its scalar operand: no LDS staging, no VGPRs.  This is
-// the HBM-bound regime of one client (sec. 3.1): two multiply-adds per
-// 4-byte DB word.
-constexpr int STREAM_THREADS = 256;
-static_assert(STREAM_THREADS == VALU_STRIP, "a streaming block covers one DB strip");
-constexpr int STREAM_UNROLL = 15;
-
-template <int MB>
-__global__ void __launch_bounds__(STREAM_THREADS)
-rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
-                     uint32_t *__restrict__ out, uint32_t d0, uint32_t d1, uint32_t L, uint32_t N,
-                     uint32_t nblk_n, ModQ4 mods) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t nb = bid % nblk_n;
-    const uint32_t gg = bid / nblk_n;          // point group over all primes
-    const uint32_t G = N / 4;
-    const uint32_t l = gg / G, g = gg % G;
-    const ModQ mq = mods.m[l];
-    const uint32_t n = nb * STREAM_THREADS + tid;
-    if (n >= d1) return;
-
-    // the block's columns are strip nb: its rows are one contiguous run
-    const uint32_t w = valu_strip_width(nb, d1);
-    const uint4 *dcol = db + valu_strip_base(gg, nb, d0, d1) + tid;
-    // query vector (m, k) at qv + m*mstride + k*kstride (16-byte units)
-    const uint4 *qv = reinterpret_cast<const uint4 *>(qry + (uint64_t)l * N + 4 * g);
-    const uint64_t kstride = (uint64_t)L * N / 4, mstride = (uint64_t)d0 * kstride;
-    uint64_t acc[MB][4];
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) acc[i][s] = 0;
-
-    uint32_t k = 0;
-    for (; k + STREAM_UNROLL <= d0; k += STREAM_UNROLL) {
-        uint4 v[STREAM_UNROLL];
-#pragma unroll
-        for (int u = 0; u < STREAM_UNROLL; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * w);
-#pragma unroll
-        for (int u = 0; u < STREAM_UNROLL; ++u)
-#pragma unroll
-            for (int i = 0; i < MB; ++i) mad4(acc[i], qv[i * mstride + (k + u) * kstride], v[u]);
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc[i][s] = lazy_fold(acc[i][s], mq);
-    }
-    if (k < d0) {   // ragged tail: fewer than fifteen rows
-        for (; k < d0; ++k) {
-            const uint4 v = ld_nt(dcol + (uint64_t)k * w);
-#pragma unroll
-            for (int i = 0; i < MB; ++i) mad4(acc[i], qv[i * mstride + k * kstride], v);
-        }
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc[i][s] = lazy_fold(acc[i][s], mq);
-    }
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        uint4 r;
-        r.x = reduce64(acc[i][0], mq);
-        r.y = reduce64(acc[i][1], mq);
-        r.z = reduce64(acc[i][2], mq);
-        r.w = reduce64(acc[i][3], mq);
-        *reinterpret_cast<uint4 *>(out + (((uint64_t)i * d1 + n) * L + l) * N + 4 * g) = r;
-    }
 }
 
 // ---------------------------------------------------------- query ingest
@@ -260,23 +185,8 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
     const ModQ4 mods = pack_mods(db);
     const uint4 *dbv = reinterpret_cast<const uint4 *>(db.valu.data);
     if (m_rows <= 8) {
-        const uint32_t nblk_n = (p.d1 + STREAM_THREADS - 1) / STREAM_THREADS;
-        const uint64_t blocks = groups * nblk_n;
-        if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
-        dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
-#define PIR_STREAM_CASE(MBv)                                                                   \
-    case MBv:                                                                                  \
-        rowsel_stream_kernel<MBv><<<grid, block, 0, st>>>(dbv, q, out, p.d0, p.d1, p.nprimes,  \
-                                                          p.n, nblk_n, mods);                  \
-        break;
-        switch (m_rows) {
-            PIR_STREAM_CASE(2)
-            PIR_STREAM_CASE(4)
-            PIR_STREAM_CASE(6)
-            PIR_STREAM_CASE(8)
-            default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
-        }
-#undef PIR_STREAM_CASE
+        launch_rowsel_stream(db, q, B, out, st);
+        return;
     } else {
         const uint32_t nblk_m = (m_rows + BM - 1) / BM;
         const uint32_t nblk_n = (p.d1 + BN - 1) / BN;

@@ -124,6 +124,8 @@ struct pir_server {
     uint64_t next_chunk = 0, steps = 0, admitted = 0, completed = 0;
 
     ~pir_server() {
+        int prev = -1;
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
         if (device_bytes || st) {
             (void)hipSetDevice(device);
             if (st) (void)hipStreamSynchronize(st);
@@ -134,6 +136,7 @@ struct pir_server {
         dev_free(stage);
         dev_free(row_dst_dev);
         if (st) (void)hipStreamDestroy(st);
+        if (prev >= 0) (void)hipSetDevice(prev);
     }
 
     // device bytes for `cap` client slots
@@ -261,7 +264,7 @@ pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_
         const uint32_t max_clients = o.max_clients ? o.max_clients : 256;
         PIR_REQUIRE(max_clients <= 4096, "max_clients must be <= 4096");
         PIR_REQUIRE(o.pipeline <= 4, "pipeline must be 1..4");
-        PIR_HIP(hipSetDevice(db->device));
+        DeviceGuard dg(db->device);
         auto *srv = new pir_server();
         try {
             srv->db = db;
@@ -311,7 +314,7 @@ pir_status pir_serve_step(pir_server *srv, const pir_request *arrivals, uint32_t
         PIR_REQUIRE(n_arrivals == 0 || arrivals != nullptr, "arrivals is NULL");
         PIR_REQUIRE(cap == 0 || done != nullptr, "done is NULL");
         if (n_done) *n_done = 0;
-        PIR_HIP(hipSetDevice(srv->device));
+        DeviceGuard dg(srv->device);
         const double t = now_s();
         const auto &p = srv->db->p;
         const size_t qb = (size_t)2 * p.d0 * srv->db->slots() * 4, ob = (size_t)2 * p.d1 * srv->db->slots() * 4;
