@@ -73,12 +73,6 @@ ModQ make_modq(uint32_t q) {
     m.q = q;
     m.r32 = (uint32_t)((1ull << 32) % q);
     m.mu = (uint64_t)(((unsigned __int128)1 << 64) / q);
-    m.moff = ((1ull << 63) / q) * q;
-    uint64_t w = 1 % q;
-    for (int s = 0; s < 7; ++s) {
-        m.w[s] = (uint32_t)w;
-        w = (w << 8) % q;
-    }
     m.fold2 = m.r32 >= (1u << 28) ? 1u : 0u;
     m.qd = (double)q;
     m.qinv = 1.0 / (double)q;

@@ -70,17 +70,12 @@ pir_status guarded(F &&body) {
 //   q      the prime, < 2^30
 //   r32    2^32 mod q           (folding a 64-bit sum: hi*2^32 + lo = hi*r32 + lo)
 //   mu     floor(2^64 / q)      (Barrett reduction of a 64-bit value)
-//   moff   the largest multiple of q not above 2^63 (shifts a signed 64-bit
-//          sum of magnitude < 2^62 into [0, 2^64) without changing it mod q)
-//   w[s]   2^(8s) mod q, s = 0..6 (weights of the digit-product groups)
 //   qd, qinv    q and 1/q in binary64 (exact-integer reductions, see modarith.h)
 //   c32, c47    2^32 mod q and 2^47 mod q in binary64
 struct ModQ {
     uint32_t q;
     uint32_t r32;
     uint64_t mu;
-    uint64_t moff;
-    uint32_t w[7];
     uint32_t fold2;   // 1 when r32 >= 2^28: two folds keep fifteen more products exact
     double qd, qinv, c32, c47;
 };
