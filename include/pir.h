@@ -250,6 +250,20 @@ pir_status pir_ntt_forward(const uint32_t *in_dev, uint32_t *out_dev, uint32_t c
 pir_status pir_ntt_inverse(const uint32_t *in_dev, uint32_t *out_dev, uint32_t count,
                            uint32_t n, uint32_t q, void *hip_stream);
 
+/* Kernel timing, for benchmarks and profiling.  After pir_kernel_timing(1),
+ * every pir_rowsel and pir_rowsel_grouped call records two HIP events on
+ * its stream around its main kernel: the streaming kernel (VALU path,
+ * B <= 4), the tiled kernel (VALU path, B > 4) or the persistent INT8 GEMM
+ * (MFMA path).  Query ingest, output transposes and scratch allocation
+ * fall outside the events.  pir_kernel_time_read waits for every recorded
+ * event, stores how many launches were timed and their summed duration in
+ * milliseconds, and forgets them (PIR_EINVAL if an out pointer is NULL).
+ * pir_kernel_timing(0) stops recording and drops unread events.  Off by
+ * default; recording is process-wide, costs two event records per call,
+ * and must not be enabled while a stream is being captured into a graph. */
+pir_status pir_kernel_timing(int enable);
+pir_status pir_kernel_time_read(uint32_t *launches, double *total_ms);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char *pir_last_error(void);
 

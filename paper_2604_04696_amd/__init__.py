@@ -65,6 +65,8 @@ SIGNATURES = {
     "pir_server_destroy": (None, [_vp]),
     "pir_ntt_forward": (_i32, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "pir_ntt_inverse": (_i32, [_vp, _vp, _u32, _u32, _u32, _vp]),
+    "pir_kernel_timing": (_i32, [_i32]),
+    "pir_kernel_time_read": (_i32, [ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_double)]),
     "pir_last_error": (ctypes.c_char_p, []),
     "pir_version": (ctypes.c_char_p, []),
     "pir_synth_query": (_i32, [_vp, _u64, _u32, _u32, _u32, _u32, _u32,
@@ -336,6 +338,18 @@ def pir_ntt_inverse(src, out, n: int, q: int, stream=None):
     count = src.numel() // n
     _check(lib().pir_ntt_inverse(_ptr(src, "src"), _ptr(out, "out"), count, n, q,
                                  _stream(stream)), "pir_ntt_inverse")
+
+
+def pir_kernel_timing(enable: bool):
+    """Start (True) or stop (False) event timing of each call's main kernel."""
+    _check(lib().pir_kernel_timing(1 if enable else 0), "pir_kernel_timing")
+
+
+def pir_kernel_time_read():
+    """(launches, total_ms) of the main-kernel launches timed since the last read."""
+    n, ms = _u32(), ctypes.c_double()
+    _check(lib().pir_kernel_time_read(ctypes.byref(n), ctypes.byref(ms)), "pir_kernel_time_read")
+    return n.value, ms.value
 
 
 def pir_last_error() -> str:

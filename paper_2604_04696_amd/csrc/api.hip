@@ -1,8 +1,12 @@
 // C-ABI entry points of libpir.so: validation, DB management and dispatch.
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 #include "modarith.h"
@@ -31,6 +35,56 @@ void dev_free(void *p) {
 
 DevBuf::DevBuf(size_t n) : ptr(dev_alloc(n)), bytes(n) {}
 DevBuf::~DevBuf() { dev_free(ptr); }
+
+StreamScratch::StreamScratch(size_t bytes, hipStream_t s) : st(s) {
+    if (bytes == 0) return;
+    const hipError_t e = hipMallocAsync(&ptr, bytes, st);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        PIR_FAIL(e == hipErrorOutOfMemory ? PIR_ENOMEM : PIR_EDEVICE, "hipMallocAsync(%zu bytes) failed: %s",
+                 bytes, hipGetErrorString(e));
+    }
+}
+StreamScratch::~StreamScratch() {
+    if (ptr) (void)hipFreeAsync(ptr, st);
+}
+
+// ------------------------------------------------------------- kernel timer
+// Recorded (start, stop) pairs wait here until pir_kernel_time_read.
+static std::atomic<bool> g_timing{false};
+static std::mutex g_timing_mu;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timed;
+
+static void drop_timed_locked() {
+    for (auto &e : g_timed) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    g_timed.clear();
+}
+
+KernelTimer::Scope::Scope(hipStream_t s) : st(s) {
+    if (!g_timing.load(std::memory_order_relaxed)) return;
+    PIR_HIP(hipEventCreate(&start));
+    const hipError_t e = hipEventRecord(start, st);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(start);
+        start = nullptr;
+        PIR_FAIL(PIR_EDEVICE, "hipEventRecord failed: %s", hipGetErrorString(e));
+    }
+}
+KernelTimer::Scope::~Scope() {
+    if (!start) return;
+    hipEvent_t stop = nullptr;
+    if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, st) != hipSuccess) {
+        if (stop) (void)hipEventDestroy(stop);
+        (void)hipEventDestroy(start);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.emplace_back(start, stop);
+}
 
 bool env_flag(const char *name) {
     const char *v = std::getenv(name);
@@ -170,6 +224,39 @@ using namespace pir;
 
 extern "C" {
 
+pir_status pir_kernel_timing(int enable) {
+    return pir::guarded([&] {
+        std::lock_guard<std::mutex> lk(pir::g_timing_mu);
+        pir::g_timing.store(enable != 0);
+        if (!enable) pir::drop_timed_locked();
+    });
+}
+
+pir_status pir_kernel_time_read(uint32_t *launches, double *total_ms) {
+    return pir::guarded([&] {
+        PIR_REQUIRE(launches && total_ms, "launches and total_ms must not be NULL");
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+        {
+            std::lock_guard<std::mutex> lk(pir::g_timing_mu);
+            timed.swap(pir::g_timed);
+        }
+        double sum = 0;
+        hipError_t err = hipSuccess;
+        for (auto &e : timed) {
+            float ms = 0;
+            hipError_t r = hipEventSynchronize(e.second);
+            if (r == hipSuccess) r = hipEventElapsedTime(&ms, e.first, e.second);
+            if (r != hipSuccess && err == hipSuccess) err = r;
+            sum += ms;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        if (err != hipSuccess) PIR_FAIL(PIR_EDEVICE, "reading kernel timing events failed: %s", hipGetErrorString(err));
+        *launches = (uint32_t)timed.size();
+        *total_ms = sum;
+    });
+}
+
 const char *pir_last_error(void) { return g_last_error.c_str(); }
 
 const char *pir_version(void) { return "pir-rowsel-mi355x 0.1 (gfx950)"; }
@@ -257,9 +344,9 @@ pir_status pir_db_load_ntt(pir_db *db, const uint32_t *src, uint32_t row0, uint3
         // coefficient domain: NTT into a stream-ordered temporary, in row chunks
         // of at most ~1 GiB, then build the layouts from it
         const uint32_t chunk = (uint32_t)std::max<uint64_t>(1, (1ull << 30) / (row_words * 4));
-        uint32_t *tmp = nullptr;
         const uint32_t rows_tmp = std::min(chunk, nrows);
-        PIR_HIP(hipMallocAsync((void **)&tmp, (size_t)rows_tmp * row_words * 4, st));
+        StreamScratch buf((size_t)rows_tmp * row_words * 4, st);
+        uint32_t *tmp = buf.as<uint32_t>();
         for (uint32_t r = 0; r < nrows; r += rows_tmp) {
             const uint32_t nr = std::min(rows_tmp, nrows - r);
             const uint32_t *s = src + (uint64_t)r * row_words;
@@ -271,7 +358,6 @@ pir_status pir_db_load_ntt(pir_db *db, const uint32_t *src, uint32_t row0, uint3
             if (db->layouts & PIR_LAYOUT_VALU) launch_db_layout_valu(*db, tmp, row0 + r, nr, st);
             if (db->layouts & PIR_LAYOUT_MFMA) launch_db_layout_mfma(*db, tmp, row0 + r, nr, st);
         }
-        PIR_HIP(hipFreeAsync(tmp, st));
     });
 }
 

@@ -173,6 +173,33 @@ struct DeviceGuard {
 void *dev_alloc(size_t bytes);   // throws PIR_ENOMEM
 void dev_free(void *p);
 
+// Stream-ordered temporary: hipMallocAsync on `st` at construction,
+// hipFreeAsync on the same stream when the scope ends (also when a later
+// step of the call throws).  Allocation failure throws PIR_ENOMEM.
+struct StreamScratch {
+    void *ptr = nullptr;
+    hipStream_t st = nullptr;
+    StreamScratch(size_t bytes, hipStream_t s);
+    ~StreamScratch();
+    StreamScratch(const StreamScratch &) = delete;
+    StreamScratch &operator=(const StreamScratch &) = delete;
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Timing of each RowSel path's main kernel (pir_kernel_timing): while
+// enabled, a Scope records a pair of HIP events on the launch stream around
+// the launches made during its lifetime.
+struct KernelTimer {
+    struct Scope {
+        explicit Scope(hipStream_t st);
+        ~Scope();
+        Scope(const Scope &) = delete;
+        Scope &operator=(const Scope &) = delete;
+        hipStream_t st;
+        hipEvent_t start = nullptr;
+    };
+};
+
 bool env_flag(const char *name);
 
 // ---------------------------------------------------------------- launchers

@@ -17,6 +17,13 @@ __device__ __forceinline__ uint4 ld_nt(const uint4 *p) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// 16-byte store marked non-temporal (written once, read back only by a later
+// kernel).
+__device__ __forceinline__ void st_nt(uint4 *p, const uint4 &x) {
+    const u32x4 v = {x.x, x.y, x.z, x.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+}
+
 // hi*2^32 + lo  ==  hi*r32 + lo  (mod q).  For x < 2^64 the result is below
 // 2^32*r32 + 2^32; a single v_mad_u64_u32.
 __device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r32) {

@@ -646,14 +646,16 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
     const uint32_t mp = (2 * B + 31) / 32 * 32;
     const size_t qbytes = (mfma_query_scratch_bytes(db, B) + 255) / 256 * 256;
     const size_t sbytes = (size_t)db.slots() * mp * staging_stride(db.p.d1) * 4;
-    int8_t *scratch = nullptr;
-    PIR_HIP(hipMallocAsync((void **)&scratch, qbytes + sbytes, st));
+    StreamScratch buf(qbytes + sbytes, st);
+    int8_t *scratch = buf.as<int8_t>();
     uint32_t *stage = reinterpret_cast<uint32_t *>(scratch + qbytes);
     launch_query_digits(db, q, B, scratch, st);
     const MfmaJob job = make_mfma_job(db, scratch, stage, B, 0, pick_wm(B));
-    launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
+    {
+        KernelTimer::Scope timed(st);
+        launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
+    }
     launch_out_transpose(stage, out, 2 * B, mp, db.p.d1, (uint32_t)db.slots(), st);
-    PIR_HIP(hipFreeAsync(scratch, st));
 }
 
 // ------------------------------------------------------------- grouped
@@ -866,7 +868,10 @@ void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hi
         if (pl.item_job[i] != SIZE_MAX)
             launch_query_digits(*items[i].db, items[i].q_dev, items[i].B,
                                 const_cast<int8_t *>(pl.jobs[pl.item_job[i]].qd), st);
-    launch_mfma_jobs(pl.jobs[0], pl.jobs_dev, (uint32_t)pl.jobs.size(), pl.total_tiles, st);
+    {
+        KernelTimer::Scope timed(st);
+        launch_mfma_jobs(pl.jobs[0], pl.jobs_dev, (uint32_t)pl.jobs.size(), pl.total_tiles, st);
+    }
     for (uint32_t i = 0; i < count; ++i) {
         if (pl.item_job[i] == SIZE_MAX) continue;
         const MfmaJob &j = pl.jobs[pl.item_job[i]];

@@ -6,11 +6,19 @@
 // DbLayoutValu): a thread owns four consecutive points of one prime (one
 // 16-byte vector) and one column; a block owns one 256-column strip of one
 // point group, whose D0 rows are one contiguous run that the block reads
-// front to back with non-temporal 16-byte loads.  The query and the output
-// stay in the boundary layout.  Products of residues are < 2^60; a 64-bit
-// sum absorbs fifteen of them on top of a folded remainder, every fifteen
-// rows the sum is folded (hi*2^32 + lo -> hi*(2^32 mod q) + lo) and one
+// front to back with non-temporal 16-byte loads, eight rows per batch, the
+// next batch in flight while the current one is multiplied.  The query is
+// read in the boundary layout.  Products of residues are < 2^60; a 64-bit
+// sum absorbs fifteen of them on top of a folded remainder, the sum is
+// folded (hi*2^32 + lo -> hi*(2^32 mod q) + lo) after every batch and one
 // Barrett reduction at the end yields the canonical residue.
+//
+// Results leave the kernel through a staging buffer [L*N/4][2B][D1] of
+// 16-byte vectors: every wave stores one contiguous kilobyte with
+// non-temporal stores, and a transpose kernel then writes the boundary
+// layout.  Storing into the boundary layout directly scatters one 16-byte
+// piece per lane over as many cache lines, and those partial-line writes,
+// interleaved with the DB stream, cost about a tenth of the kernel's time.
 #include "common.h"
 #include "modarith.h"
 
@@ -37,12 +45,13 @@ __device__ __forceinline__ void mad4s(uint64_t (&acc)[4], const uint4 &a, const 
 // 4-byte DB word.
 constexpr int STREAM_THREADS = 256;
 static_assert(STREAM_THREADS == VALU_STRIP, "a streaming block covers one DB strip");
-constexpr int STREAM_UNROLL = 15;
+constexpr int STREAM_ROWS = 8;   // rows per load batch and per fold
+static_assert(STREAM_ROWS <= 15, "a 64-bit sum absorbs at most fifteen products between folds");
 
 template <int MB>
 __global__ void __launch_bounds__(STREAM_THREADS)
 rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
-                     uint32_t *__restrict__ out, uint32_t d0, uint32_t d1, uint32_t L, uint32_t N,
+                     uint4 *__restrict__ stage, uint32_t d0, uint32_t d1, uint32_t L, uint32_t N,
                      uint32_t nblk_n, ModQ4s mods) {
     const uint32_t tid = threadIdx.x;
     const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -66,30 +75,45 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[i][s] = 0;
 
-    uint32_t k = 0;
-    for (; k + STREAM_UNROLL <= d0; k += STREAM_UNROLL) {
-        uint4 v[STREAM_UNROLL];
+    auto load = [&](uint4 (&v)[STREAM_ROWS], uint32_t k) {
 #pragma unroll
-        for (int u = 0; u < STREAM_UNROLL; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * w);
-#pragma unroll
-        for (int u = 0; u < STREAM_UNROLL; ++u)
-#pragma unroll
-            for (int i = 0; i < MB; ++i) mad4s(acc[i], qv[i * mstride + (k + u) * kstride], v[u]);
+        for (int u = 0; u < STREAM_ROWS; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * w);
+    };
+    auto fold_all = [&]() {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[i][s] = lazy_fold(acc[i][s], mq);
+    };
+    auto mul = [&](const uint4 (&v)[STREAM_ROWS], uint32_t k) {
+#pragma unroll
+        for (int u = 0; u < STREAM_ROWS; ++u)
+#pragma unroll
+            for (int i = 0; i < MB; ++i) mad4s(acc[i], qv[i * mstride + (k + u) * kstride], v[u]);
+        fold_all();
+    };
+
+    // full batches, two buffers: batch j+1 is loaded while batch j is multiplied
+    const uint32_t nfull = d0 / STREAM_ROWS;
+    uint4 a[STREAM_ROWS], b[STREAM_ROWS];
+    if (nfull > 0) load(a, 0);
+    uint32_t j = 0;
+    for (; j + 2 <= nfull; j += 2) {
+        load(b, (j + 1) * STREAM_ROWS);
+        mul(a, j * STREAM_ROWS);
+        if (j + 2 < nfull) load(a, (j + 2) * STREAM_ROWS);
+        mul(b, (j + 1) * STREAM_ROWS);
     }
-    if (k < d0) {   // ragged tail: fewer than fifteen rows
-        for (; k < d0; ++k) {
+    if (j < nfull) mul(a, j * STREAM_ROWS);   // odd batch count: `a` holds the last one
+    // ragged tail: fewer than STREAM_ROWS rows
+    const uint32_t k0 = nfull * STREAM_ROWS;
+    if (k0 < d0) {
+        for (uint32_t k = k0; k < d0; ++k) {
             const uint4 v = ld_nt(dcol + (uint64_t)k * w);
 #pragma unroll
             for (int i = 0; i < MB; ++i) mad4s(acc[i], qv[i * mstride + k * kstride], v);
         }
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc[i][s] = lazy_fold(acc[i][s], mq);
+        fold_all();
     }
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
@@ -98,10 +122,35 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
         r.y = reduce64(acc[i][1], mq);
         r.z = reduce64(acc[i][2], mq);
         r.w = reduce64(acc[i][3], mq);
-        *reinterpret_cast<uint4 *>(out + (((uint64_t)i * d1 + n) * L + l) * N + 4 * g) = r;
+        st_nt(stage + ((uint64_t)gg * MB + i) * d1 + n, r);
     }
 }
 
+// Staging [GG][C] -> boundary output [C][GG], in 16-byte vectors, GG = L*N/4
+// point groups and C = 2B*D1 output rows: word ((m*D1 + n)*L + l)*N + 4g of
+// the output is vector (m*D1 + n)*GG + gg.  Tiles of 32 groups x 64 rows pass
+// through LDS, so both sides move runs of at least 512 bytes.
+constexpr int TR_G = 32, TR_C = 64;
+
+__global__ void __launch_bounds__(256)
+stream_out_transpose_kernel(const uint4 *__restrict__ stage, uint4 *__restrict__ out, uint64_t GG,
+                            uint64_t C, uint32_t nblk_c) {
+    __shared__ uint4 tile[TR_G][TR_C + 1];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t c0 = (uint64_t)(blockIdx.x % nblk_c) * TR_C;
+    const uint64_t g0 = (uint64_t)(blockIdx.x / nblk_c) * TR_G;
+#pragma unroll
+    for (int r = 0; r < TR_G * TR_C / 256; ++r) {
+        const uint32_t gi = r * 4 + tid / 64, ci = tid % 64;
+        if (g0 + gi < GG && c0 + ci < C) tile[gi][ci] = ld_nt(stage + (g0 + gi) * C + c0 + ci);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TR_G * TR_C / 256; ++r) {
+        const uint32_t ci = r * 8 + tid / 32, gi = tid % 32;
+        if (g0 + gi < GG && c0 + ci < C) out[(c0 + ci) * GG + g0 + gi] = tile[gi][ci];
+    }
+}
 
 void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, hipStream_t st) {
     const auto &p = db.p;
@@ -112,15 +161,27 @@ void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint3
     const uint4 *dbv = reinterpret_cast<const uint4 *>(db.valu.data);
     const uint32_t nblk_n = (p.d1 + STREAM_THREADS - 1) / STREAM_THREADS;
     const uint64_t blocks = groups * nblk_n;
-    if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
-    dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
-    switch (m_rows) {
-        case 2: rowsel_stream_kernel<2><<<grid, block, 0, st>>>(dbv, q, out, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-        case 4: rowsel_stream_kernel<4><<<grid, block, 0, st>>>(dbv, q, out, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-        case 6: rowsel_stream_kernel<6><<<grid, block, 0, st>>>(dbv, q, out, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-        case 8: rowsel_stream_kernel<8><<<grid, block, 0, st>>>(dbv, q, out, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-        default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
+    const uint64_t C = (uint64_t)m_rows * p.d1;
+    const uint64_t nblk_c = (C + TR_C - 1) / TR_C;
+    const uint64_t tblocks = nblk_c * ((groups + TR_G - 1) / TR_G);
+    if (blocks >= (1ull << 31) || tblocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
+
+    StreamScratch scratch(groups * C * sizeof(uint4), st);   // [groups][2B][D1] vectors
+    uint4 *stage = scratch.as<uint4>();
+    {
+        KernelTimer::Scope timed(st);
+        dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
+        switch (m_rows) {
+            case 2: rowsel_stream_kernel<2><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+            case 4: rowsel_stream_kernel<4><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+            case 6: rowsel_stream_kernel<6><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+            case 8: rowsel_stream_kernel<8><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+            default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
+        }
+        PIR_LAUNCH_CHECK();
     }
+    stream_out_transpose_kernel<<<(uint32_t)tblocks, 256, 0, st>>>(stage, reinterpret_cast<uint4 *>(out), groups, C,
+                                                                 (uint32_t)nblk_c);
     PIR_LAUNCH_CHECK();
 }
 

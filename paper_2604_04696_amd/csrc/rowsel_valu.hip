@@ -196,15 +196,15 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
         const uint64_t iblocks = (uint64_t)(mp / 16) * nkb * ngb;
         if (blocks >= (1ull << 31) || iblocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
         // stream-ordered scratch for the group-major query copy
-        uint4 *qv = nullptr;
-        PIR_HIP(hipMallocAsync((void **)&qv, groups * p.d0 * mp * sizeof(uint4), st));
+        StreamScratch buf(groups * p.d0 * mp * sizeof(uint4), st);
+        uint4 *qv = buf.as<uint4>();
         valu_query_kernel<<<(uint32_t)iblocks, 256, 0, st>>>(reinterpret_cast<const uint4 *>(q), qv, m_rows, mp,
                                                              p.d0, (uint32_t)groups, nkb, ngb);
         PIR_LAUNCH_CHECK();
+        KernelTimer::Scope timed(st);
         rowsel_tiled_kernel<<<(uint32_t)blocks, TILE_THREADS, 0, st>>>(
             dbv, qv, out, m_rows, mp, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
         PIR_LAUNCH_CHECK();
-        PIR_HIP(hipFreeAsync(qv, st));
         return;
     }
     PIR_LAUNCH_CHECK();

@@ -103,6 +103,14 @@ def test_null_arguments(L):
     assert "NULL" in pir.pir_last_error()
 
 
+def test_kernel_timing_without_a_device(L):
+    assert L.pir_kernel_time_read(None, None) == pir.PIR_EINVAL
+    assert L.pir_kernel_timing(0) == pir.PIR_OK
+    n, ms = ctypes.c_uint32(7), ctypes.c_double(1.0)
+    assert L.pir_kernel_time_read(ctypes.byref(n), ctypes.byref(ms)) == pir.PIR_OK
+    assert (n.value, ms.value) == (0, 0.0)
+
+
 def test_ntt_helper_rejects_bad_modulus(L):
     assert L.pir_ntt_forward(None, None, 1, 1024, 1073707011, None) == pir.PIR_EINVAL
     assert L.pir_ntt_inverse(None, None, 1, 1000, 1073707009, None) == pir.PIR_EINVAL

@@ -88,6 +88,9 @@ SHAPES = [
     # on the streaming (B <= 4) and the tiled (B > 4) VALU kernels
     (16, synth.PRIMES_N4096, 33, 520, 2),
     (16, synth.PRIMES_N4096, 70, 520, 9),
+    # streaming kernel: an even count of 8-row batches and no ragged tail,
+    # fewer point groups than one output-transpose tile
+    (32, synth.PRIMES_N4096, 48, 260, 1),
     # D0 above the 2048-row int32 accumulation chunk of the MFMA path
     (16, synth.PRIMES_N4096, 4200, 5, 2),
     # a prime with large 2^32 mod q (954376193: the recombination takes the
@@ -192,3 +195,27 @@ def test_error_paths_on_device(pir):
         pir.pir_db_load_ntt(db, empty_u32(2 * d1 * 2 * n), 7, 2, pir.PIR_DOMAIN_NTT)
     pir.pir_rowsel(db, q, out, pir.PIR_PATH_VALU, B=0)     # B = 0 is a no-op
     torch.cuda.synchronize()
+
+
+def test_kernel_timing_counts_main_kernels(pir):
+    # one timed launch per call: streaming (B <= 4), tiled (B > 4) and INT8 GEMM
+    n, primes, d0, d1 = 64, synth.PRIMES_N4096, 40, 24
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1))
+    pir.pir_db_load_ntt(db, to_dev(synth.db_coeffs(60, d0, d1, len(primes), n)),
+                        domain=pir.PIR_DOMAIN_COEFF)
+    calls = [(1, pir.PIR_PATH_VALU), (5, pir.PIR_PATH_VALU), (3, pir.PIR_PATH_MFMA_I8)]
+    args = [(to_dev(synth.query_uniform(61, B, d0, primes, n)), empty_u32(B * 2 * d1 * len(primes) * n), path)
+            for B, path in calls]
+    pir.pir_kernel_timing(True)
+    try:
+        for q, out, path in args:
+            pir.pir_rowsel(db, q, out, path)
+        launches, ms = pir.pir_kernel_time_read()
+        assert launches == len(calls) and ms > 0
+        assert pir.pir_kernel_time_read() == (0, 0.0)
+    finally:
+        pir.pir_kernel_timing(False)
+    q, out, path = args[0]
+    pir.pir_rowsel(db, q, out, path)    # not recorded once disabled
+    torch.cuda.synchronize()
+    assert pir.pir_kernel_time_read() == (0, 0.0)
