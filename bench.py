@@ -289,18 +289,6 @@ def main():
     db = build_db(pir, w, pir.PIR_LAYOUT_VALU | pir.PIR_LAYOUT_MFMA)
     log(f"DB built in {time.time() - t0:.1f} s")
 
-    # ------------------------------------------- measured HBM reference
-    # a STREAM-style pass on the same GPU: 2 GiB read + 2 GiB written
-    ref_src = torch.zeros(1 << 29, dtype=torch.int32, device="cuda")
-    ref_dst = torch.empty_like(ref_src)
-    for _ in range(2):
-        torch.bitwise_not(ref_src, out=ref_dst)
-    torch.cuda.synchronize()
-    ref_ms = statistics.median(timed_calls(lambda: torch.bitwise_not(ref_src, out=ref_dst), 10))
-    copy_gbs = 2 * ref_src.numel() * 4 / (ref_ms * 1e-3) / 1e9
-    del ref_src, ref_dst
-    torch.cuda.empty_cache()
-
     # ---------------------------------------------------------- headline
     q1 = make_query(pir, w, 1, w.seed)
     out1 = torch.empty(2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
@@ -311,6 +299,11 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # the DB load released its temporaries; HBM-bound kernels run ~4% slower
+    # for a second or two after device memory is released, so let that pass
+    # (setup, not part of a step: every timed call still allocates and frees
+    # its own stream-ordered scratch)
+    time.sleep(2.0)
     st = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
@@ -330,6 +323,21 @@ def main():
     call_ms = statistics.mean(a.elapsed_time(b) for a, b in evs)
     kmean = ktotal / launches
     log(f"B=1 VALU: wall {wall / args.steps * 1e3:.3f} ms/step, call {call_ms:.3f} ms, kernel {kmean:.3f} ms")
+
+    # ------------------------------------------- measured HBM reference
+    # a STREAM-style pass on the same GPU: 2 GiB read + 2 GiB written.  Taken
+    # after the headline: releasing device memory slows HBM-bound kernels on
+    # this GPU for up to a few seconds afterwards (about 4% on the streaming
+    # kernel after a 4 GiB free), so nothing is freed before the timed steps.
+    ref_src = torch.zeros(1 << 29, dtype=torch.int32, device="cuda")
+    ref_dst = torch.empty_like(ref_src)
+    for _ in range(2):
+        torch.bitwise_not(ref_src, out=ref_dst)
+    torch.cuda.synchronize()
+    ref_ms = statistics.median(timed_calls(lambda: torch.bitwise_not(ref_src, out=ref_dst), 10))
+    copy_gbs = 2 * ref_src.numel() * 4 / (ref_ms * 1e-3) / 1e9
+    del ref_src, ref_dst
+    torch.cuda.empty_cache()
 
     ms_step = wall / args.steps * 1e3
     db_gbs = w.db_bytes / (ms_step * 1e-3) / 1e9

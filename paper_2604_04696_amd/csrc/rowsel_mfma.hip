@@ -74,7 +74,7 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
         const uint32_t e = tid + 256 * j, rr = e / 4096, kk = (e / 64) % 64, pp = e % 64;
         const uint32_t k = k0 + kk, r = r0 + rr;
         v[j] = r < r_valid && k >= klo && k < khi && p0 + pp < P
-                   ? src[(uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp]
+                   ? __builtin_nontemporal_load(src + (uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp)
                    : 0u;
     }
 #pragma unroll
@@ -103,7 +103,7 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
         }
         int8_t *o = dst + ((((uint64_t)(p0 + pp) * 4 + d) * (kp / 64) + kc / 64) * RS + row0 + r) * 64 + kc % 64;
         if (inside) {
-            *reinterpret_cast<uint4 *>(o) = make_uint4(w[0], w[1], w[2], w[3]);
+            st_nt(reinterpret_cast<uint4 *>(o), make_uint4(w[0], w[1], w[2], w[3]));
         } else {
             for (int i = 0; i < 16; ++i) {
                 const uint32_t k = kc + i;
@@ -468,7 +468,7 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const uint32_t m = ct.m0 + wmi * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                        pt[(uint64_t)m * ct.sstride] = res[r];
+                        __builtin_nontemporal_store(res[r], pt + (uint64_t)m * ct.sstride);
                     }
                 }
                 after_store = true;
@@ -513,7 +513,7 @@ out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ 
     for (int j = 0; j < 4; ++j) {
         const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
         v[j] = p0 + pi < P && n0 + 4 * nq < d1
-                   ? *reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq)
+                   ? ld_nt(reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq))
                    : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
@@ -529,8 +529,8 @@ out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ 
     for (int j = 0; j < 4; ++j) {
         const uint32_t e = tid + 256 * j, ni = e / 16, pq = e % 16;
         if (n0 + ni < d1 && p0 + 4 * pq < P)
-            *reinterpret_cast<uint4 *>(out + ((uint64_t)m * d1 + n0 + ni) * P + p0 + 4 * pq) =
-                *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]);
+            st_nt(reinterpret_cast<uint4 *>(out + ((uint64_t)m * d1 + n0 + ni) * P + p0 + 4 * pq),
+                  *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]));
     }
 }
 

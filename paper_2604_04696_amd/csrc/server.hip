@@ -18,6 +18,7 @@
 
 #include "common.h"
 #include "mfma.h"
+#include "modarith.h"
 
 namespace pir {
 
@@ -46,7 +47,7 @@ serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restr
     for (int j = 0; j < 4; ++j) {
         const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
         v[j] = p0 + pi < cp && n0 + 4 * nq < d1
-                   ? *reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq)
+                   ? ld_nt(reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq))
                    : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
@@ -62,8 +63,8 @@ serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restr
     for (int j = 0; j < 4; ++j) {
         const uint32_t e = tid + 256 * j, ni = e / 16, pq = e % 16;
         if (n0 + ni < d1 && p0 + 4 * pq < cp)
-            *reinterpret_cast<uint4 *>(dst + (uint64_t)(n0 + ni) * pall + p_begin + p0 + 4 * pq) =
-                *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]);
+            st_nt(reinterpret_cast<uint4 *>(dst + (uint64_t)(n0 + ni) * pall + p_begin + p0 + 4 * pq),
+                  *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]));
     }
 }
 
