@@ -304,24 +304,20 @@ def main():
     # (setup, not part of a step: every timed call still allocates and frees
     # its own stream-ordered scratch)
     time.sleep(2.0)
-    st = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
     pir.pir_kernel_timing(True)      # HIP events around the streaming kernel, on its stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(st)
+    for _ in range(args.steps):
         step()
-        b.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launches, ktotal = pir.pir_kernel_time_read()
     pir.pir_kernel_timing(False)
     if launches != args.steps:
         raise RuntimeError(f"timed {launches} kernel launches for {args.steps} steps")
-    call_ms = statistics.mean(a.elapsed_time(b) for a, b in evs)
     kmean = ktotal / launches
+    # whole calls (kernel, output transpose, scratch), event-timed after the steps
+    call_ms = statistics.mean(timed_calls(step, min(args.steps, 10)))
     log(f"B=1 VALU: wall {wall / args.steps * 1e3:.3f} ms/step, call {call_ms:.3f} ms, kernel {kmean:.3f} ms")
 
     # ------------------------------------------- measured HBM reference
