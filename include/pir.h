@@ -133,6 +133,23 @@ void pir_db_free(pir_db *db);
 pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
                       uint32_t *out_dev, pir_path path, void *hip_stream);
 
+/* RowSel on selector ciphertexts given in the coefficient domain, the form
+ * query expansion produces them in (sec. 2.2): every query polynomial is
+ * first taken to the NTT domain with the convention of pir_db_load_ntt
+ * (ahat_i = a(psi^(2i+1)), natural order; sec. 2.4.1), then multiplied as
+ * in pir_rowsel, whose output it equals bit for bit on the transformed
+ * query.
+ * q_coeff_dev: [B][2][D0][L][N] coefficients; limb l is read mod q_l (any
+ *         uint32 value is accepted).  out_dev as for pir_rowsel and must not
+ *         overlap q_coeff_dev.
+ * MFMA path: one launch transforms the polynomials in LDS and writes the
+ * signed-digit query planes the GEMM reads, so no NTT-domain copy of the
+ * query is stored.  VALU path: the transform writes an NTT-domain copy of
+ * the query into stream-ordered scratch (the query's size) first.  Same
+ * path choice, errors and stream semantics as pir_rowsel. */
+pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff_dev, uint32_t B,
+                            uint32_t *out_dev, pir_path path, void *hip_stream);
+
 /* One RowSel instance of a grouped call. */
 typedef struct {
     const pir_db *db;

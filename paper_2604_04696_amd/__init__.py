@@ -56,6 +56,7 @@ SIGNATURES = {
     "pir_db_layouts": (_u32, [_vp]),
     "pir_db_free": (None, [_vp]),
     "pir_rowsel": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
+    "pir_rowsel_coeff": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
     "pir_rowsel_grouped": (_i32, [_vp, _u32, _i32, _vp]),
     "pir_rowsel_grouped_tile": (_i32, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "pir_clock": (ctypes.c_double, []),
@@ -198,7 +199,7 @@ def pir_db_free(db: Db):
         lib().pir_db_free(h)
 
 
-def pir_rowsel(db: Db, query, out, path: int = PIR_PATH_AUTO, stream=None, B: int | None = None):
+def _rowsel_args(db: Db, query, out, B):
     _need_u32(query, "query")
     _need_u32(out, "out")
     per_q = 2 * db.d0 * db.nprimes * db.n
@@ -206,9 +207,18 @@ def pir_rowsel(db: Db, query, out, path: int = PIR_PATH_AUTO, stream=None, B: in
     B = query.numel() // per_q if B is None else B
     if query.numel() < B * per_q or out.numel() < B * per_o:
         raise ValueError("query/out smaller than B clients")
-    qp = _ptr(query, "query") if B else 0
-    op = _ptr(out, "out") if B else 0
+    return (_ptr(query, "query") if B else 0), B, (_ptr(out, "out") if B else 0)
+
+
+def pir_rowsel(db: Db, query, out, path: int = PIR_PATH_AUTO, stream=None, B: int | None = None):
+    qp, B, op = _rowsel_args(db, query, out, B)
     _check(lib().pir_rowsel(db.handle, qp, B, op, path, _stream(stream)), "pir_rowsel")
+
+
+def pir_rowsel_coeff(db: Db, query_coeff, out, path: int = PIR_PATH_AUTO, stream=None, B: int | None = None):
+    """RowSel on a coefficient-domain query (transformed to the NTT domain by the library)."""
+    qp, B, op = _rowsel_args(db, query_coeff, out, B)
+    _check(lib().pir_rowsel_coeff(db.handle, qp, B, op, path, _stream(stream)), "pir_rowsel_coeff")
 
 
 class pir_rowsel_item(ctypes.Structure):

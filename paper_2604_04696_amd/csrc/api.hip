@@ -209,13 +209,23 @@ void check_rowsel_args(const pir_db *db, const uint32_t *q, uint32_t B, const ui
 }
 
 void rowsel_one(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, pir_path path,
-                hipStream_t st) {
+                hipStream_t st, bool q_coeff) {
     if (B == 0) return;
     DeviceGuard dg(db.device);
-    if (env_flag("PIR_VALIDATE")) check_residues(q, (uint64_t)B * 2 * db.p.d0 * db.slots(), db.p, st);
+    const uint64_t qwords = (uint64_t)B * 2 * db.p.d0 * db.slots();
+    if (!q_coeff && env_flag("PIR_VALIDATE")) check_residues(q, qwords, db.p, st);
     const pir_path use = resolve_path(db, B, path);
-    if (use == PIR_PATH_VALU) launch_rowsel_valu(db, q, B, out, st);
-    else launch_rowsel_mfma(db, q, B, out, st);
+    if (use == PIR_PATH_VALU) {
+        if (q_coeff) {
+            StreamScratch qn(qwords * 4, st);   // NTT-domain copy of the query
+            launch_query_ntt(db, q, B, qn.as<uint32_t>(), st);
+            launch_rowsel_valu(db, qn.as<uint32_t>(), B, out, st);
+        } else {
+            launch_rowsel_valu(db, q, B, out, st);
+        }
+    } else {
+        launch_rowsel_mfma(db, q, B, out, st, q_coeff);
+    }
 }
 
 }  // namespace pir
@@ -366,6 +376,14 @@ pir_status pir_rowsel(const pir_db *db, const uint32_t *q, uint32_t B, uint32_t 
     return guarded([&] {
         check_rowsel_args(db, q, B, out);
         rowsel_one(*db, q, B, out, path, as_stream(stream));
+    });
+}
+
+pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff, uint32_t B, uint32_t *out, pir_path path,
+                            void *stream) {
+    return guarded([&] {
+        check_rowsel_args(db, q_coeff, B, out);
+        rowsel_one(*db, q_coeff, B, out, path, as_stream(stream), true);
     });
 }
 

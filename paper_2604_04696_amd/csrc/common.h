@@ -214,8 +214,14 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
                         hipStream_t st);
 void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                           hipStream_t st);   // 2B <= 8
+// q_coeff: the query is in the coefficient domain (fused NTT + digit planes)
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
-                        hipStream_t st);
+                        hipStream_t st, bool q_coeff = false);
+// Query front end (coefficient-domain queries): the NTT-domain query in the
+// boundary layout, or directly the MFMA path's query digit planes.
+void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uint32_t *q_ntt, hipStream_t st);
+void launch_query_ntt_digits(const pir_db &db, const uint32_t *q_coeff, uint32_t B, int8_t *qd,
+                             hipStream_t st);
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st);
 void release_group_plans();
@@ -223,7 +229,7 @@ void release_group_plans();
 bool group_plan_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *bm, uint32_t *bn);
 void check_rowsel_args(const pir_db *db, const uint32_t *q, uint32_t B, const uint32_t *out);
 void rowsel_one(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, pir_path path,
-                hipStream_t st);
+                hipStream_t st, bool q_coeff = false);
 void launch_validate_residues(const uint32_t *x, uint64_t count_per_limb_block, uint32_t n,
                               uint32_t nprimes, const uint32_t *q, uint64_t total,
                               uint32_t *flag, hipStream_t st);

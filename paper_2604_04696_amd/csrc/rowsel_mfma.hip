@@ -640,7 +640,7 @@ void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows
 }
 
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
-                        hipStream_t st) {
+                        hipStream_t st, bool q_coeff) {
     // scratch: query digit planes [P][4][Kp/64][Mp][64], then the output
     // staging [P][Mp][sstride]
     const uint32_t mp = (2 * B + 31) / 32 * 32;
@@ -649,7 +649,8 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
     StreamScratch buf(qbytes + sbytes, st);
     int8_t *scratch = buf.as<int8_t>();
     uint32_t *stage = reinterpret_cast<uint32_t *>(scratch + qbytes);
-    launch_query_digits(db, q, B, scratch, st);
+    if (q_coeff) launch_query_ntt_digits(db, q, B, scratch, st);
+    else launch_query_digits(db, q, B, scratch, st);
     const MfmaJob job = make_mfma_job(db, scratch, stage, B, 0, pick_wm(B));
     {
         KernelTimer::Scope timed(st);

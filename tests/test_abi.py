@@ -103,6 +103,11 @@ def test_null_arguments(L):
     assert "NULL" in pir.pir_last_error()
 
 
+def test_rowsel_coeff_rejects_null_db(L):
+    assert L.pir_rowsel_coeff(None, None, 1, None, 0, None) == pir.PIR_EINVAL
+    assert "db is NULL" in pir.pir_last_error()
+
+
 def test_kernel_timing_without_a_device(L):
     assert L.pir_kernel_time_read(None, None) == pir.PIR_EINVAL
     assert L.pir_kernel_timing(0) == pir.PIR_OK
