@@ -214,6 +214,38 @@ def serving_section(pir, n_requests: int, loads):
             "runs": runs, "in_mix_equals_alone": same, "steps": st.steps}
 
 
+def query_front_section(pir, db, w, q_ntt, out, ntt_domain_ms):
+    """64 clients with the query in the coefficient domain (the same words as
+    the NTT-domain query, read as coefficients): the fused front end
+    (pir_rowsel_coeff, MFMA path) against the library's NTT helper on the
+    query followed by pir_rowsel, and against pir_rowsel on an NTT-domain
+    query (no transform)."""
+    import torch
+    rows = w.clients * 2 * w.d0
+    # the helper transforms contiguous polynomials: each prime's limbs, gathered
+    # once outside the timed calls (the same bytes as the interleaved query)
+    srcs = [q_ntt.view(rows, w.nprimes, w.n)[:, l, :].contiguous() for l in range(w.nprimes)]
+    dsts = [torch.empty_like(x) for x in srcs]
+
+    def two_pass():   # transform, then RowSel (on q_ntt: the same work as on the transformed words)
+        for l, q in enumerate(w.primes):
+            pir.pir_ntt_forward(srcs[l], dsts[l], w.n, q)
+        pir.pir_rowsel(db, q_ntt, out, pir.PIR_PATH_MFMA_I8)
+
+    def fused():
+        pir.pir_rowsel_coeff(db, q_ntt, out, pir.PIR_PATH_MFMA_I8)
+
+    res = {}
+    for name, fn in (("fused_ms", fused), ("ntt_then_rowsel_ms", two_pass)):
+        fn()
+        torch.cuda.synchronize()
+        res[name] = round(statistics.median(timed_calls(fn, 7)), 3)
+    res["ntt_domain_rowsel_ms"] = round(ntt_domain_ms, 3)
+    res["query_gib"] = round(rows * w.slots * 4 / 2**30, 2)
+    del srcs, dsts
+    return res
+
+
 def make_query_sub(pir, w, sub):
     import torch
     import synth
@@ -379,6 +411,8 @@ def main():
         m["mfma_frac"] = round(m["i8_tops"] / I8_PEAK_TOPS, 4)
         res["mfma_over_valu"] = round(res["valu"]["ms"] / m["ms"], 2)
         line["batched_b64"] = res
+        line["query_front_b64"] = query_front_section(pir, db, wb, qb, ob, m["ms"])
+        log(f"query front end: {line['query_front_b64']}")
         del qb, ob
 
     pir.pir_db_free(db)

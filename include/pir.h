@@ -58,7 +58,7 @@ typedef enum {
 #define PIR_MAX_PRIMES 4
 
 /* Ring and database parameters.
- *   n       ring degree N: a power of two, 8 <= N <= 65536
+ *   n       ring degree N: a power of two, 8 <= N <= 16384
  *   nprimes L: number of RNS primes, 1..4 (the paper uses four, sec. 2.4.1)
  *   q[l]    primes q < 2^30 with q = 1 (mod 2N) (needed for the negacyclic
  *           NTT); the < 2^30 bound is what keeps up to fifteen 60-bit
@@ -142,11 +142,10 @@ pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
  * q_coeff_dev: [B][2][D0][L][N] coefficients; limb l is read mod q_l (any
  *         uint32 value is accepted).  out_dev as for pir_rowsel and must not
  *         overlap q_coeff_dev.
- * MFMA path: one launch transforms the polynomials in LDS and writes the
- * signed-digit query planes the GEMM reads, so no NTT-domain copy of the
- * query is stored.  VALU path: the transform writes an NTT-domain copy of
- * the query into stream-ordered scratch (the query's size) first.  Same
- * path choice, errors and stream semantics as pir_rowsel. */
+ * One launch transforms the query into an NTT-domain copy in stream-ordered
+ * scratch (the query's size), which the chosen path then reads as
+ * pir_rowsel would.  Same path choice, errors and stream semantics as
+ * pir_rowsel. */
 pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff_dev, uint32_t B,
                             uint32_t *out_dev, pir_path path, void *hip_stream);
 

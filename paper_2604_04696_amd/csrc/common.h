@@ -214,14 +214,12 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
                         hipStream_t st);
 void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                           hipStream_t st);   // 2B <= 8
-// q_coeff: the query is in the coefficient domain (fused NTT + digit planes)
+// q_coeff: the query is in the coefficient domain (transformed first)
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st, bool q_coeff = false);
-// Query front end (coefficient-domain queries): the NTT-domain query in the
-// boundary layout, or directly the MFMA path's query digit planes.
+// Query front end: coefficient-domain query -> NTT-domain query, both in the
+// boundary layout [B][2][D0][L][N].
 void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uint32_t *q_ntt, hipStream_t st);
-void launch_query_ntt_digits(const pir_db &db, const uint32_t *q_coeff, uint32_t B, int8_t *qd,
-                             hipStream_t st);
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st);
 void release_group_plans();

@@ -5,24 +5,26 @@
 // sec. 2.4.1), so a query that arrives as coefficients (the form query
 // expansion leaves it in, sec. 2.2) needs the forward negacyclic NTT of each
 // of its 2B*D0*L polynomials first, with the convention of the DB load:
-// ahat_i = a(psi^(2i+1)), natural order.
+// ahat_i = a(psi^(2i+1)), natural order.  One launch transforms the whole
+// query into an NTT-domain copy in the boundary layout, which the chosen
+// path then consumes like any query (the MFMA path through its digit-plane
+// ingest).
 //
-// INT8 MFMA path: one launch transforms the polynomials and writes the
-// signed-digit query planes [L*N][4][Kp/64][Mp][64] that the persistent GEMM
-// reads, so no NTT-domain copy of the query is ever stored.  A block takes
-// KG polynomials of one row m and prime l with consecutive k (KG = 8 at
-// N <= 4096), transforms them in LDS (Cooley-Tukey with psi powers in
-// bit-reversed order, as the DB load's NTT) and, for every point, writes the
-// KG digit bytes of each digit plane as one KG-byte piece of the plane's
-// 64-byte row.  The 64/KG blocks that fill one row are consecutive in the
-// launch order and run on one XCD, so the pieces meet in its L2 before the
-// line goes to HBM.  Digits of k >= D0 (padding up to Kp) are written as
-// zero; padding rows 2B <= m < Mp are not written at all: an output row of
-// the GEMM depends on its own query row only, and rows m >= 2B never reach
-// the output.
+// For N >= 256 the transform is register-blocked (query_ntt_reg_kernel: 16
+// values per thread, up to four butterfly stages per LDS exchange, three
+// exchanges at N = 4096); smaller rings use one LDS stage per barrier with
+// KG polynomials of consecutive k per block (query_ntt_kernel).  On the
+// 2 GiB query of 64 clients (N = 4096, two primes, D0 = 512) the transform
+// takes ~1.9 ms, against ~4.3 ms for the per-polynomial NTT of the DB load
+// and ~7 ms for the one-stage-per-barrier form over 8 polynomials.
 //
-// VALU path: the polynomials are transformed into an NTT-domain copy of the
-// query in stream-ordered scratch, which the VALU kernels then read.
+// Writing the MFMA path's digit planes straight from the transform (KG bytes
+// of each 64-byte plane row per block) was measured and is not used: those
+// scattered 8-byte stores ran at a few hundred GB/s (7.9 ms for the 2 GiB
+// 64-client query), far slower than the NTT-domain copy plus the ingest.
+// One pass cannot write whole plane rows: a row needs the same point of all
+// the 64 k of a chunk, i.e. 64 full polynomials (1 MiB at N = 4096) in one
+// block.
 #include "common.h"
 #include "mfma.h"
 #include "modarith.h"
@@ -42,34 +44,31 @@ static uint32_t qf_group(uint32_t n) { return std::min<uint32_t>(8, QF_LDS_WORDS
 
 template <int KG>
 __global__ void __launch_bounds__(QF_THREADS)
-query_ntt_digits_kernel(const uint32_t *__restrict__ q, int8_t *__restrict__ qd, uint32_t mp, uint32_t d0,
-                        uint32_t L, uint32_t n, uint32_t logn, uint32_t nkc, QfPrimes pr) {
+query_ntt_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint32_t d0, uint32_t L,
+                 uint32_t n, uint32_t logn, QfPrimes pr) {
     extern __shared__ uint32_t s[];   // [KG][n]
     const uint32_t tid = threadIdx.x;
-    const uint32_t kgroups = nkc * (64 / KG);
-    uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t kgroups = (d0 + KG - 1) / KG;
+    uint32_t b = blockIdx.x;
     const uint32_t kg = b % kgroups;
     b /= kgroups;
     const uint32_t l = b % L;
     const uint32_t m = b / L;
     const uint32_t k0 = kg * KG;
+    const uint32_t kn = min((uint32_t)KG, d0 - k0);   // polynomials of this block
     const uint32_t qv = pr.q[l];
 
-    // load: polynomial (m, k, l) is n contiguous words of the query
-    for (uint32_t e = tid; e < KG * n; e += QF_THREADS) {
-        const uint32_t kk = e >> logn, i = e & (n - 1), k = k0 + kk;
-        uint32_t v = 0;
-        if (k < d0) {
-            v = q[((uint64_t)m * d0 + k) * L * n + (uint64_t)l * n + i];
-            v = v >= qv ? v % qv : v;
-        }
-        s[e] = v;
+    // polynomial (m, k, l) is n contiguous words of the query
+    for (uint32_t e = tid; e < kn * n; e += QF_THREADS) {
+        const uint32_t kk = e >> logn, i = e & (n - 1);
+        uint32_t v = q[((uint64_t)m * d0 + k0 + kk) * L * n + (uint64_t)l * n + i];
+        s[e] = v >= qv ? v % qv : v;
     }
     __syncthreads();
     const uint32_t *tw = pr.tw[l], *tws = tw + n;
     const uint32_t half = n >> 1;
     for (uint32_t mm = 1, lt = logn - 1; mm < n; mm <<= 1, --lt) {
-        for (uint32_t e = tid; e < KG * half; e += QF_THREADS) {
+        for (uint32_t e = tid; e < kn * half; e += QF_THREADS) {
             const uint32_t kk = e >> (logn - 1), bb = e & (half - 1);
             const uint32_t i = bb >> lt;
             const uint32_t j = (i << (lt + 1)) + (bb & ((1u << lt) - 1));
@@ -81,37 +80,112 @@ query_ntt_digits_kernel(const uint32_t *__restrict__ q, int8_t *__restrict__ qd,
         }
         __syncthreads();
     }
-
-    // LDS position i holds point j = bitrev(i) of every polynomial; each
-    // point's four digit planes receive KG bytes (k0 .. k0+KG-1) of one row
-    const uint64_t plane = (uint64_t)mp * 64;                 // bytes of one (point, digit, chunk) plane
-    int8_t *base = qd + (uint64_t)(k0 / 64) * plane + (uint64_t)m * 64 + (k0 % 64);
-    for (uint32_t i = tid; i < n; i += QF_THREADS) {
+    // LDS position i holds point bitrev(i): lanes read LDS in order (no bank
+    // conflicts) and scatter within the polynomial's 16 KiB (whole lines are
+    // completed by the same block)
+    for (uint32_t e = tid; e < kn * n; e += QF_THREADS) {
+        const uint32_t kk = e >> logn, i = e & (n - 1);
         const uint32_t j = __brev(i) >> (32 - logn);
-        uint32_t dg[KG];
+        qn[((uint64_t)m * d0 + k0 + kk) * L * n + (uint64_t)l * n + j] = s[e];
+    }
+}
+
+// Register-blocked transform for N >= 256: a polynomial is handled by
+// T = N/16 threads that each keep 16 of its values in registers.  The
+// butterfly stages (bit x of the pair distance, from logN-1 down to 0) run in
+// chunks of up to four: during a chunk the register index r of a thread
+// covers four index bits [lo, lo+4) (for the last chunk, bits [0, 4)), so
+// every pair of the chunk's stages is local to one thread; between chunks
+// the values are redistributed through LDS (padded one word per 16).  The
+// element index of (thread t, register r) with register bits starting at lo:
+//   e = (t mod 2^lo) | r << lo | (t >> lo) << (lo + 4).
+// The butterfly of stage x on pair (e, e + 2^x) uses the psi power of group
+// e >> (x+1) among N >> (x+1) groups, exactly as the one-stage-per-barrier
+// form.  A last exchange writes point bitrev(e) so that global stores are in
+// natural point order and coalesced.
+constexpr int QR = 16;   // values per thread
+
+__device__ __forceinline__ uint32_t qf_pad(uint32_t e) { return e + (e >> 4); }
+__device__ __forceinline__ uint32_t qf_elem(uint32_t t, uint32_t r, uint32_t lo) {
+    return (t & ((1u << lo) - 1)) | (r << lo) | ((t >> lo) << (lo + 4));
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(QF_THREADS)
+query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint32_t d0, uint32_t L,
+                     uint32_t ppb, QfPrimes pr) {
+    constexpr uint32_t n = 1u << LOGN, logn = LOGN;
+    extern __shared__ uint32_t s[];                  // ppb polynomials of n + n/16 words
+    constexpr uint32_t T = n / QR;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t pi = tid / T, t = tid % T;       // polynomial of the block, thread within it
+    const uint32_t kgroups = (d0 + ppb - 1) / ppb;
+    uint32_t b = blockIdx.x;
+    const uint32_t kg = b % kgroups;
+    b /= kgroups;
+    const uint32_t l = b % L;
+    const uint32_t m = b / L;
+    const uint32_t k = kg * ppb + pi;
+    const bool live = pi < ppb && k < d0;            // uniform per polynomial's threads
+    const uint32_t qv = pr.q[l];
+    const uint32_t *tw = pr.tw[l], *tws = tw + n;
+    uint32_t *poly = s + pi * (n + n / 16);
+    const uint64_t off = ((uint64_t)m * d0 + k) * L * n + (uint64_t)l * n;
+
+    uint32_t v[QR];
+    uint32_t lo = logn - 4;                          // register bits of the first chunk
+    if (live) {
 #pragma unroll
-        for (int kk = 0; kk < KG; ++kk) dg[kk] = split_digits(s[kk * n + i]);
-        const uint64_t p = (uint64_t)l * n + j;
+        for (int r = 0; r < QR; ++r) {
+            const uint32_t x = q[off + qf_elem(t, r, lo)];
+            v[r] = x >= qv ? x % qv : x;
+        }
+    }
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            uint8_t bytes[KG];
+    for (int hi = (int)logn; hi > 0; hi -= 4) {
+        const int clo = hi - 4 > 0 ? hi - 4 : 0;     // lowest stage of this chunk
+        const uint32_t rlo = (uint32_t)clo;          // registers cover bits [rlo, rlo + 4)
+        if (rlo != lo) {                              // redistribute through LDS
+            __syncthreads();
+            if (live) {
 #pragma unroll
-            for (int kk = 0; kk < KG; ++kk) bytes[kk] = (uint8_t)(dg[kk] >> (8 * d));
-            int8_t *dst = base + (p * 4 + d) * nkc * plane;
-            if (KG == 8) {
-                uint2 w;
-                __builtin_memcpy(&w, bytes, 8);
-                *reinterpret_cast<uint2 *>(dst) = w;
-            } else if (KG == 4) {
-                uint32_t w;
-                __builtin_memcpy(&w, bytes, 4);
-                *reinterpret_cast<uint32_t *>(dst) = w;
-            } else {
-                uint16_t w;
-                __builtin_memcpy(&w, bytes, 2);
-                *reinterpret_cast<uint16_t *>(dst) = w;
+                for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, r, lo))] = v[r];
+            }
+            __syncthreads();
+            if (live) {
+#pragma unroll
+                for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(qf_elem(t, r, rlo))];
+            }
+            lo = rlo;
+        }
+        if (live) {
+#pragma unroll
+            for (int x = hi - 1; x >= clo; --x) {
+                const uint32_t bit = 1u << (x - (int)lo), mgroups = n >> (x + 1);
+#pragma unroll
+                for (int r = 0; r < QR; ++r) {
+                    if (r & bit) continue;
+                    const uint32_t e = qf_elem(t, r, lo);
+                    const uint32_t gi = mgroups + (e >> (x + 1));
+                    const uint32_t u = v[r];
+                    const uint32_t w = mul_shoup(v[r | bit], tw[gi], tws[gi], qv);
+                    v[r] = add_mod(u, w, qv);
+                    v[r | bit] = sub_mod(u, w, qv);
+                }
             }
         }
+    }
+    // element e holds point bitrev(e): place points in natural order, then
+    // store coalesced
+    __syncthreads();
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < QR; ++r) poly[qf_pad(__brev(qf_elem(t, r, lo)) >> (32 - logn))] = v[r];
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < QR; ++r) qn[off + t + r * T] = poly[qf_pad(t + r * T)];
     }
 }
 
@@ -120,11 +194,8 @@ static void qf_attr(const void *fn, size_t lds) {
     PIR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
 }
 
-void launch_query_ntt_digits(const pir_db &db, const uint32_t *q_coeff, uint32_t B, int8_t *qd,
-                             hipStream_t st) {
+void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uint32_t *q_ntt, hipStream_t st) {
     const auto &p = db.p;
-    const uint32_t mp = (2 * B + 31) / 32 * 32;
-    const uint32_t nkc = db.mfma.kp / 64;
     const uint32_t kgs = qf_group(p.n);
     uint32_t logn = 0;
     while ((1u << logn) < p.n) ++logn;
@@ -134,38 +205,53 @@ void launch_query_ntt_digits(const pir_db &db, const uint32_t *q_coeff, uint32_t
         pr.tw[l] = t.fwd;
         pr.q[l] = p.q[l];
     }
-    const uint64_t blocks = 2ull * B * p.nprimes * nkc * (64 / kgs);   // rows m < 2B only
+    if (p.n >= 256) {
+        // register-blocked form: polynomials per block so that a block has
+        // up to 1024 threads (N/16 per polynomial)
+        const uint32_t ppb = std::max<uint32_t>(1, QF_THREADS / (p.n / QR));
+        const uint64_t blocks = 2ull * B * p.nprimes * ((p.d0 + ppb - 1) / ppb);
+        if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "query front-end launch too large");
+        const size_t lds = (size_t)ppb * (p.n + p.n / 16) * sizeof(uint32_t);
+        const uint32_t threads = ppb * (p.n / QR);
+        auto go = [&](auto kern) {
+            qf_attr(reinterpret_cast<const void *>(kern), lds);
+            kern<<<(uint32_t)blocks, threads, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, ppb, pr);
+        };
+        switch (logn) {
+            case 8: go(&query_ntt_reg_kernel<8>); break;
+            case 9: go(&query_ntt_reg_kernel<9>); break;
+            case 10: go(&query_ntt_reg_kernel<10>); break;
+            case 11: go(&query_ntt_reg_kernel<11>); break;
+            case 12: go(&query_ntt_reg_kernel<12>); break;
+            case 13: go(&query_ntt_reg_kernel<13>); break;
+            case 14: go(&query_ntt_reg_kernel<14>); break;
+            default: PIR_FAIL(PIR_EINVAL, "unsupported ring dimension %u", p.n);
+        }
+        PIR_LAUNCH_CHECK();
+        return;
+    }
+    const uint64_t blocks = 2ull * B * p.nprimes * ((p.d0 + kgs - 1) / kgs);
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "query front-end launch too large");
     const size_t lds = (size_t)kgs * p.n * sizeof(uint32_t);
     switch (kgs) {
         case 8:
-            qf_attr(reinterpret_cast<const void *>(&query_ntt_digits_kernel<8>), lds);
-            query_ntt_digits_kernel<8><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(
-                q_coeff, qd, mp, p.d0, p.nprimes, p.n, logn, nkc, pr);
+            qf_attr(reinterpret_cast<const void *>(&query_ntt_kernel<8>), lds);
+            query_ntt_kernel<8><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n,
+                                                                           logn, pr);
             break;
         case 4:
-            qf_attr(reinterpret_cast<const void *>(&query_ntt_digits_kernel<4>), lds);
-            query_ntt_digits_kernel<4><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(
-                q_coeff, qd, mp, p.d0, p.nprimes, p.n, logn, nkc, pr);
+            qf_attr(reinterpret_cast<const void *>(&query_ntt_kernel<4>), lds);
+            query_ntt_kernel<4><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n,
+                                                                           logn, pr);
             break;
         case 2:
-            qf_attr(reinterpret_cast<const void *>(&query_ntt_digits_kernel<2>), lds);
-            query_ntt_digits_kernel<2><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(
-                q_coeff, qd, mp, p.d0, p.nprimes, p.n, logn, nkc, pr);
+            qf_attr(reinterpret_cast<const void *>(&query_ntt_kernel<2>), lds);
+            query_ntt_kernel<2><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n,
+                                                                           logn, pr);
             break;
         default: PIR_FAIL(PIR_EINVAL, "unsupported ring dimension %u", p.n);
     }
     PIR_LAUNCH_CHECK();
-}
-
-void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uint32_t *q_ntt, hipStream_t st) {
-    const auto &p = db.p;
-    const uint64_t polys = 2ull * B * p.d0;   // per prime; polynomial (m, k) of prime l at ((m*D0 + k)*L + l)*N
-    for (uint32_t l = 0; l < p.nprimes; ++l) {
-        const NttTables &t = ntt_tables(p.q[l], p.n);
-        launch_ntt(q_coeff + (uint64_t)l * p.n, q_ntt + (uint64_t)l * p.n, polys, (uint64_t)p.nprimes * p.n,
-                   (uint64_t)p.nprimes * p.n, t, false, st);
-    }
 }
 
 }  // namespace pir

@@ -649,8 +649,15 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
     StreamScratch buf(qbytes + sbytes, st);
     int8_t *scratch = buf.as<int8_t>();
     uint32_t *stage = reinterpret_cast<uint32_t *>(scratch + qbytes);
-    if (q_coeff) launch_query_ntt_digits(db, q, B, scratch, st);
-    else launch_query_digits(db, q, B, scratch, st);
+    if (q_coeff) {
+        // coefficient-domain query: transform into an NTT-domain copy, then
+        // the usual ingest (scratch freed when the call's work has passed)
+        StreamScratch qn((size_t)B * 2 * db.p.d0 * db.slots() * 4, st);
+        launch_query_ntt(db, q, B, qn.as<uint32_t>(), st);
+        launch_query_digits(db, qn.as<uint32_t>(), B, scratch, st);
+    } else {
+        launch_query_digits(db, q, B, scratch, st);
+    }
     const MfmaJob job = make_mfma_job(db, scratch, stage, B, 0, pick_wm(B));
     {
         KernelTimer::Scope timed(st);

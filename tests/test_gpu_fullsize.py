@@ -71,3 +71,36 @@ def test_batched_sampled_and_paths_identical(pir, big_db):
     clients, cols = [0, 37, 63], [5, 300]
     want = oracle_columns(w, cols, clients, w.seed, w.clients)
     assert np.array_equal(got[clients][:, :, cols], want)
+
+
+def test_coeff_query_batched_full_size(pir, big_db):
+    # coefficient-domain query at the 64-client size: the fused front end on
+    # the MFMA path equals the NTT helper followed by pir_rowsel on every
+    # word, and the oracle (its own NTT of the sampled clients' polynomials)
+    # on sampled columns
+    w = W64
+    key = synth.stream_key(w.seed, synth.TAG_QUERY, 9)
+    count = w.clients * 2 * w.d0 * w.slots
+    qc = torch.empty(count, dtype=torch.int32, device="cuda")
+    pir.pir_synth_query(qc, key, 0, w.clients, w.d0, w.primes, w.n)    # residues < q_l as coefficients
+    qn = torch.empty_like(qc)
+    rows = w.clients * 2 * w.d0
+    for l, q in enumerate(w.primes):
+        src = qc.view(rows, w.nprimes, w.n)[:, l, :].contiguous()
+        dst = torch.empty_like(src)
+        pir.pir_ntt_forward(src, dst, w.n, q)
+        qn.view(rows, w.nprimes, w.n)[:, l, :] = dst
+        del src, dst
+    a = empty_u32(w.clients * 2 * w.d1 * w.slots)
+    b = empty_u32(w.clients * 2 * w.d1 * w.slots)
+    print("rowsel_coeff B=64 mfma full size", flush=True)
+    pir.pir_rowsel_coeff(big_db, qc, a, pir.PIR_PATH_MFMA_I8)
+    pir.pir_rowsel(big_db, qn, b, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    clients, cols = [0, 41], [7, 400]
+    qsel = np_u32(qc).reshape(w.clients, 2, w.d0, w.nprimes, w.n)[clients]
+    coeffs = synth.db_coeffs(w.dbseed, w.d0, w.d1, w.nprimes, w.n, cols=cols)
+    want = oracle.rowsel(oracle.ntt_db(qsel, w.primes), oracle.ntt_db(coeffs, w.primes), w.primes)
+    got = np_u32(a).reshape(w.clients, 2, w.d1, w.nprimes, w.n)
+    assert np.array_equal(got[clients][:, :, cols], want)
