@@ -15,7 +15,7 @@
 // exchanges at N = 4096); smaller rings use one LDS stage per barrier with
 // KG polynomials of consecutive k per block (query_ntt_kernel).  On the
 // 2 GiB query of 64 clients (N = 4096, two primes, D0 = 512) the transform
-// takes ~1.9 ms, against ~4.3 ms for the per-polynomial NTT of the DB load
+// takes ~1.45 ms, against ~4.3 ms for the per-polynomial NTT of the DB load
 // and ~7 ms for the one-stage-per-barrier form over 8 polynomials.
 //
 // Writing the MFMA path's digit planes straight from the transform (KG bytes
@@ -37,6 +37,7 @@ constexpr uint32_t QF_LDS_WORDS = 32768;   // 128 KiB of polynomials per block
 struct QfPrimes {
     const uint32_t *tw[PIR_MAX_PRIMES];   // forward twiddles: [n] powers, [n] Shoup companions
     uint32_t q[PIR_MAX_PRIMES];
+    uint32_t r1[PIR_MAX_PRIMES];          // floor(2^32 / q): Shoup companion of 1
 };
 
 // Polynomials per block at ring dimension n (a power of two, 8 <= n <= 16384).
@@ -101,11 +102,30 @@ query_ntt_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint
 //   e = (t mod 2^lo) | r << lo | (t >> lo) << (lo + 4).
 // The butterfly of stage x on pair (e, e + 2^x) uses the psi power of group
 // e >> (x+1) among N >> (x+1) groups, exactly as the one-stage-per-barrier
-// form.  A last exchange writes point bitrev(e) so that global stores are in
+// form; values stay in [0, 4q) between stages (lazy butterflies) and are
+// reduced once before the store.  A last exchange writes point bitrev(e) so that global stores are in
 // natural point order and coalesced.
 constexpr int QR = 16;   // values per thread
 
 __device__ __forceinline__ uint32_t qf_pad(uint32_t e) { return e + (e >> 4); }
+
+// Lazy butterfly (Harvey): inputs and outputs in [0, 4q), which fits 32 bits
+// for q < 2^30.  x is first brought into [0, 2q) (x - 2q wraps above x when
+// x < 2q, so the minimum picks the reduced value); Shoup's product without
+// its final correction lies in [0, 2q) for any 32-bit y.
+__device__ __forceinline__ void qf_bfly(uint32_t &x, uint32_t &y, uint32_t w, uint32_t ws, uint32_t q,
+                                        uint32_t q2) {
+    const uint32_t xr = min(x, x - q2);
+    const uint32_t t = y * w - __umulhi(y, ws) * q;
+    x = xr + t;
+    y = xr - t + q2;
+}
+
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ uint32_t qf_reduce4(uint32_t x, uint32_t q, uint32_t q2) {
+    x = min(x, x - q2);
+    return min(x, x - q);
+}
 __device__ __forceinline__ uint32_t qf_elem(uint32_t t, uint32_t r, uint32_t lo) {
     return (t & ((1u << lo) - 1)) | (r << lo) | ((t >> lo) << (lo + 4));
 }
@@ -135,10 +155,13 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
     uint32_t v[QR];
     uint32_t lo = logn - 4;                          // register bits of the first chunk
     if (live) {
+        // any 32-bit coefficient: x - floor(x * floor(2^32/q) / 2^32) * q is
+        // x mod q or x mod q + q, in [0, 2q) as the lazy butterflies allow
+        const uint32_t r1 = pr.r1[l];
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
             const uint32_t x = q[off + qf_elem(t, r, lo)];
-            v[r] = x >= qv ? x % qv : x;
+            v[r] = x - __umulhi(x, r1) * qv;
         }
     }
 #pragma unroll
@@ -167,10 +190,7 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
                     if (r & bit) continue;
                     const uint32_t e = qf_elem(t, r, lo);
                     const uint32_t gi = mgroups + (e >> (x + 1));
-                    const uint32_t u = v[r];
-                    const uint32_t w = mul_shoup(v[r | bit], tw[gi], tws[gi], qv);
-                    v[r] = add_mod(u, w, qv);
-                    v[r | bit] = sub_mod(u, w, qv);
+                    qf_bfly(v[r], v[r | bit], tw[gi], tws[gi], qv, 2 * qv);
                 }
             }
         }
@@ -180,7 +200,8 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
     __syncthreads();
     if (live) {
 #pragma unroll
-        for (int r = 0; r < QR; ++r) poly[qf_pad(__brev(qf_elem(t, r, lo)) >> (32 - logn))] = v[r];
+        for (int r = 0; r < QR; ++r)
+            poly[qf_pad(__brev(qf_elem(t, r, lo)) >> (32 - logn))] = qf_reduce4(v[r], qv, 2 * qv);
     }
     __syncthreads();
     if (live) {
@@ -204,6 +225,7 @@ void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uin
         const NttTables &t = ntt_tables(p.q[l], p.n);
         pr.tw[l] = t.fwd;
         pr.q[l] = p.q[l];
+        pr.r1[l] = (uint32_t)((1ull << 32) / p.q[l]);
     }
     if (p.n >= 256) {
         // register-blocked form: polynomials per block so that a block has
