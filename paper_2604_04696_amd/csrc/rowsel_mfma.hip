@@ -624,11 +624,15 @@ void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njob
     PIR_LAUNCH_CHECK();
 }
 
+// Planes of rows m < 2B only (row stride Mp): rows 2B <= m < Mp are left as
+// they are, since an output row of the GEMM depends on its own query row
+// alone and rows m >= 2B never reach the output.  The k padding up to Kp is
+// written as zero digits (it enters every valid row's sum).
 void launch_query_digits(const pir_db &db, const uint32_t *q, uint32_t B, int8_t *qd, hipStream_t st) {
     const auto &p = db.p;
     const uint32_t P = p.n * p.nprimes;
     const uint32_t mp = (2 * B + 31) / 32 * 32;
-    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, mp, 2 * B, P, db.mfma.kp, 0, p.d0, p.d0, st);
+    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, 2 * B, 2 * B, P, db.mfma.kp, 0, p.d0, p.d0, st, mp);
 }
 
 void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows, int8_t *qd,
