@@ -17,7 +17,9 @@
 // 64-row step of k is one contiguous run:
 //   DB digits    [L*N][4][Kp/64][D1][64] int8   built once at load time
 //   query digits [L*N][4][Kp/64][Mp][64] int8   built per call (ingest kernel)
-// with Kp = D0 rounded up to 64 and Mp = 2B rounded up to 32, zero padded.
+// with Kp = D0 rounded up to 64 (rows D0 <= k < Kp hold zero digits) and
+// Mp = 2B rounded up to 32 (query rows 2B <= m < Mp are not written: their
+// GEMM rows are computed and never transposed out).
 #include <algorithm>
 #include <list>
 #include <mutex>
