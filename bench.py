@@ -246,6 +246,32 @@ def query_front_section(pir, db, w, q_ntt, out, ntt_domain_ms):
     return res
 
 
+def q108_section(pir):
+    """The paper's RNS setting: four 27-bit limbs (Q ~ 2^108), D0 = 256,
+    D1 = 512 (8 GiB DB); one client (streaming kernel) and a batch of 32 on
+    both paths, median of event-timed calls."""
+    import torch
+    import synth
+    w = synth.PAPER_Q108
+    db = build_db(pir, w, pir.PIR_LAYOUT_VALU | pir.PIR_LAYOUT_MFMA)
+    time.sleep(2.0)   # let the DB build's frees settle (see the headline)
+    res = {"workload": w.name, "primes": list(w.primes), "d0": w.d0, "d1": w.d1, "db_gib": w.db_bytes / 2**30}
+    for B, path, name in ((1, pir.PIR_PATH_VALU, "b1_valu"), (w.clients, pir.PIR_PATH_MFMA_I8, "b32_mfma_i8"),
+                          (w.clients, pir.PIR_PATH_VALU, "b32_valu")):
+        q = make_query(pir, w, B, w.seed)
+        out = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
+        fn = lambda: pir.pir_rowsel(db, q, out, path)
+        fn()
+        torch.cuda.synchronize()
+        ms = statistics.median(timed_calls(fn, 10 if B == 1 else 5))
+        macs = w.slots * 2 * B * w.d0 * w.d1
+        res[name] = {"ms": round(ms, 3), "db_gbs": round(w.db_bytes / (ms * 1e-3) / 1e9, 1),
+                     "mac_per_s": macs / (ms * 1e-3)}
+        del q, out
+    pir.pir_db_free(db)
+    return res
+
+
 def make_query_sub(pir, w, sub):
     import torch
     import synth
@@ -418,6 +444,11 @@ def main():
     pir.pir_db_free(db)
     del q1, out1
     torch.cuda.empty_cache()
+
+    if not args.no_batched:
+        line["q108"] = q108_section(pir)
+        torch.cuda.empty_cache()
+        log(f"four-limb setting: {line['q108']}")
 
     if not args.no_grouped:
         log("grouped instances")

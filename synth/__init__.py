@@ -197,6 +197,10 @@ def query_uniform(seed: int, b_count: int, d0: int, primes, n: int, sub: int = 0
 # primality and q = 1 (mod 2N) on its own.
 PRIME_N1024 = (1073707009,)
 PRIMES_N4096 = (1073692673, 1073668097)
+# The paper's RNS setting: four primes in 32-bit words whose product is about
+# 2^108 -- here the four largest 27-bit primes with q = 1 (mod 8192), product
+# 2^107.99 (checked the same way as the table above).
+PRIMES_Q108 = (134176769, 134111233, 134012929, 133963777)
 
 
 @dataclass(frozen=True)
@@ -245,6 +249,9 @@ BATCHED = Workload("rowsel_n4096_l2_512x512_b64", 3, 4096, PRIMES_N4096, 512, 51
                    "uniform", db_seed=2, note="same DB as the one-client case")
 SERVE_DB = Workload("serve_n4096_l2_1024x1024", 5, 4096, PRIMES_N4096, 1024, 1024, 1,
                     "uniform", note="32 GiB resident DB; requests drawn from a 32-query pool")
+PAPER_Q108 = Workload("rowsel_n4096_l4q108_256x512_b32", 6, 4096, PRIMES_Q108, 256, 512, 32,
+                      "uniform", note="four 27-bit limbs (Q ~ 2^108) and D0 = 256 as in the paper's "
+                      "setting; 8 GiB DB; one client and a batch of 32")
 
 GROUPED_SEED = 4
 GROUPED_COUNT = 24

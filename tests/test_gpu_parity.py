@@ -91,6 +91,11 @@ SHAPES = [
     # streaming kernel: an even count of 8-row batches and no ragged tail,
     # fewer point groups than one output-transpose tile
     (32, synth.PRIMES_N4096, 48, 260, 1),
+    # the paper's RNS setting: four 27-bit limbs (Q ~ 2^108)
+    (64, synth.PRIMES_Q108, 45, 70, 1),
+    (64, synth.PRIMES_Q108, 100, 40, 3),
+    (32, synth.PRIMES_Q108, 130, 33, 9),
+    (4096, synth.PRIMES_Q108, 9, 5, 2),
     # D0 above the 2048-row int32 accumulation chunk of the MFMA path
     (16, synth.PRIMES_N4096, 4200, 5, 2),
     # a prime with large 2^32 mod q (954376193: the recombination takes the
@@ -135,8 +140,9 @@ def test_rowsel_ntt_domain_load_and_row_chunks(pir, path):
     assert np.array_equal(np_u32(out).reshape(want.shape), want)
 
 
-@pytest.mark.parametrize("case", [(32, synth.PRIMES_N4096, 1000, 40), (16, (954376193,), 4100, 8)],
-                         ids=["two_primes_1000", "split_prime_4100"])
+@pytest.mark.parametrize("case", [(32, synth.PRIMES_N4096, 1000, 40), (16, (954376193,), 4100, 8),
+                                  (16, synth.PRIMES_Q108, 2100, 6)],
+                         ids=["two_primes_1000", "split_prime_4100", "four_limbs_2100"])
 @BOTH
 def test_rowsel_all_q_minus_one(pir, path, case):
     # (q-1)^2 = 1 mod q: every output is D0 mod q; stresses the lazy 64-bit

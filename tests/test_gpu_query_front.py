@@ -50,6 +50,7 @@ SHAPES = [
     (4096, synth.PRIMES_N4096, 9, 5, 3),
     (8192, (1073692673,), 6, 3, 1),
     (16384, (1073643521,), 3, 2, 2),
+    (256, synth.PRIMES_Q108, 20, 9, 3),
 ]
 
 

@@ -2,6 +2,7 @@
 itself -- a published generator vector, direct O(N^2) evaluation in Python
 integers, exact integer convolution in numpy, Python big-integer matrix
 products, closed forms and the selection semantics of RowSel (sec. 2.2)."""
+import math
 import os
 
 import numpy as np
@@ -43,16 +44,25 @@ def _trial_prime(n):
     return True
 
 
-@pytest.mark.parametrize("n,count,table", [(1024, 1, synth.PRIME_N1024),
-                                           (4096, 2, synth.PRIMES_N4096)])
-def test_primes_are_largest_ntt_friendly(n, count, table):
-    got = oracle.ntt_primes(n, 30, count)
+@pytest.mark.parametrize("n,bits,count,table", [(1024, 30, 1, synth.PRIME_N1024),
+                                                (4096, 30, 2, synth.PRIMES_N4096),
+                                                (4096, 27, 4, synth.PRIMES_Q108)])
+def test_primes_are_largest_ntt_friendly(n, bits, count, table):
+    got = oracle.ntt_primes(n, bits, count)
     assert tuple(got) == tuple(table)
-    # independent check: primality by trial division, q = 1 mod 2N, < 2^30,
-    # and no NTT-friendly prime skipped between them and 2^30
-    cands = [x for x in range((1 << 30) - 1, table[-1] - 1, -1) if x % (2 * n) == 1]
+    # independent check: primality by trial division, q = 1 mod 2N, < 2^bits,
+    # and no NTT-friendly prime skipped between them and 2^bits
+    cands = [x for x in range((1 << bits) - 1, table[-1] - 1, -1) if x % (2 * n) == 1]
     primes = [x for x in cands if _trial_prime(x)]
     assert tuple(primes[:count]) == tuple(table)
+
+
+def test_q108_primes_product():
+    # the paper's modulus size: Q = q0 q1 q2 q3 of about 2^108 (sec. 2.4.1)
+    Q = 1
+    for q in synth.PRIMES_Q108:
+        Q *= q
+    assert 107.9 < math.log2(Q) < 108.1
 
 
 @pytest.mark.parametrize("q,n", [(1073707009, 1024), (1073692673, 4096), (1073668097, 4096),
@@ -100,7 +110,7 @@ def test_ntt_matches_direct_evaluation(n):
     assert oracle.ntt_forward(a, q, psi).tolist() == _direct_ntt(a, q, psi)
 
 
-@pytest.mark.parametrize("q,n", [(1073707009, 1024), (1073692673, 4096)])
+@pytest.mark.parametrize("q,n", [(1073707009, 1024), (1073692673, 4096), (133963777, 4096)])
 def test_ntt_matches_direct_evaluation_sampled(q, n):
     psi = oracle.psi(q, n)
     a = synth.uniform_mod(synth.stream_key(12, synth.TAG_QUERY), np.arange(n), q)
