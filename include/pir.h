@@ -60,9 +60,13 @@ typedef enum {
 /* Ring and database parameters.
  *   n       ring degree N: a power of two, 8 <= N <= 16384
  *   nprimes L: number of RNS primes, 1..4 (the paper uses four, sec. 2.4.1)
- *   q[l]    primes q < 2^30 with q = 1 (mod 2N) (needed for the negacyclic
- *           NTT); the < 2^30 bound is what keeps up to fifteen 60-bit
- *           products exact in one 64-bit accumulator
+ *   q[l]    primes with q = 1 (mod 2N) (needed for the negacyclic NTT), each
+ *           a 32-bit word.  Below 2^30 the VALU kernels keep up to fifteen
+ *           60-bit products in one 64-bit sum and the INT8 MFMA path applies;
+ *           a DB with any prime of 2^30 or more (products up to 2^64, the
+ *           paper's "32-bit primes", sec. 2.4.1) is served by the VALU layout
+ *           only, with 64-bit sums that count their wraps: creating it with
+ *           PIR_LAYOUT_MFMA fails with PIR_EUNSUPPORTED
  *   d0, d1  DB rows (selector count) and columns, each 1..65536 */
 typedef struct {
     uint32_t n;
@@ -258,7 +262,7 @@ void pir_server_destroy(pir_server *srv);
 
 /* ---------------------------------------------------------------- helpers */
 /* Negacyclic NTT / inverse NTT of `count` contiguous length-n polynomials
- * mod prime q (same convention as pir_db_load_ntt).  Not part of RowSel's
+ * mod prime q < 2^32, q = 1 (mod 2n) (same convention as pir_db_load_ntt).  Not part of RowSel's
  * hot path: used to build inputs and to check results (client-side
  * decryption).  in_dev may equal out_dev. */
 pir_status pir_ntt_forward(const uint32_t *in_dev, uint32_t *out_dev, uint32_t count,

@@ -126,6 +126,7 @@ ModQ make_modq(uint32_t q) {
     ModQ m{};
     m.q = q;
     m.r32 = (uint32_t)((1ull << 32) % q);
+    m.r64 = (uint32_t)(((unsigned __int128)1 << 64) % q);
     m.mu = (uint64_t)(((unsigned __int128)1 << 64) / q);
     m.fold2 = m.r32 >= (1u << 28) ? 1u : 0u;
     m.qd = (double)q;
@@ -142,7 +143,7 @@ void validate_params(const pir_params &p) {
                 PIR_MAX_PRIMES, p.nprimes);
     for (uint32_t l = 0; l < p.nprimes; ++l) {
         const uint32_t q = p.q[l];
-        PIR_REQUIRE(q < (1u << 30), "q[%u] = %u is not below 2^30", l, q);
+        PIR_REQUIRE(q >= 3, "q[%u] = %u is too small", l, q);
         PIR_REQUIRE(q % (2 * p.n) == 1, "q[%u] = %u is not 1 mod 2N = %u", l, q, 2 * p.n);
         PIR_REQUIRE(is_prime_u32(q), "q[%u] = %u is not prime", l, q);
     }
@@ -283,8 +284,14 @@ pir_status pir_db_create(const pir_params *params, uint32_t layouts, pir_db **ou
             db->p = *params;
             for (uint32_t l = db->p.nprimes; l < PIR_MAX_PRIMES; ++l) db->p.q[l] = 0;
             db->layouts = layouts;
+            for (uint32_t l = 0; l < db->p.nprimes; ++l) {
+                db->mod[l] = make_modq(db->p.q[l]);
+                if (db->p.q[l] >= WIDE_Q) db->wide = true;
+            }
+            if (db->wide && (layouts & PIR_LAYOUT_MFMA))
+                PIR_FAIL(PIR_EUNSUPPORTED, "the MFMA layout needs every prime below 2^30 "
+                         "(a prime of 30 to 32 bits is served by the VALU layout only)");
             PIR_HIP(hipGetDevice(&db->device));
-            for (uint32_t l = 0; l < db->p.nprimes; ++l) db->mod[l] = make_modq(db->p.q[l]);
             const uint64_t words = db->slots() * db->p.d0 * db->p.d1;
             if (layouts & PIR_LAYOUT_VALU) {
                 db->valu.data = static_cast<uint32_t *>(dev_alloc(words * 4));
@@ -449,8 +456,7 @@ static pir_status ntt_entry(const uint32_t *in, uint32_t *out, uint32_t count, u
                             void *stream, bool inverse) {
     return guarded([&] {
         PIR_REQUIRE(n >= 8 && n <= 16384 && (n & (n - 1)) == 0, "n must be a power of two in [8, 16384]");
-        PIR_REQUIRE(q < (1u << 30) && q % (2 * n) == 1 && is_prime_u32(q),
-                    "q must be a prime < 2^30 with q = 1 mod 2n");
+        PIR_REQUIRE(q % (2 * n) == 1 && is_prime_u32(q), "q must be a prime with q = 1 mod 2n");
         if (count == 0) return;
         PIR_REQUIRE(in && out, "NULL pointer");
         const NttTables &t = ntt_tables(q, n);

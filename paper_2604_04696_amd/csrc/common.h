@@ -67,8 +67,9 @@ pir_status guarded(F &&body) {
 
 // --------------------------------------------------------- modular constants
 // Per-prime constants passed to kernels by value.
-//   q      the prime, < 2^30
+//   q      the prime, < 2^32 (below 2^30 for the lazy VALU sums and the MFMA path)
 //   r32    2^32 mod q           (folding a 64-bit sum: hi*2^32 + lo = hi*r32 + lo)
+//   r64    2^64 mod q           (wide primes: wraps of a 64-bit sum)
 //   mu     floor(2^64 / q)      (Barrett reduction of a 64-bit value)
 //   qd, qinv    q and 1/q in binary64 (exact-integer reductions, see modarith.h)
 //   c32, c47    2^32 mod q and 2^47 mod q in binary64
@@ -77,8 +78,14 @@ struct ModQ {
     uint32_t r32;
     uint64_t mu;
     uint32_t fold2;   // 1 when r32 >= 2^28: two folds keep fifteen more products exact
+    uint32_t r64;
     double qd, qinv, c32, c47;
 };
+
+// Primes at or above this bound take the wide forms (64-bit intermediates,
+// no lazy sums) on the VALU path and in the NTTs; the MFMA path needs primes
+// below it.
+constexpr uint32_t WIDE_Q = 1u << 30;
 
 ModQ make_modq(uint32_t q);
 bool is_prime_u32(uint32_t q);
@@ -131,6 +138,7 @@ struct pir_db {
     pir_params p{};
     uint32_t layouts = 0;
     int device = 0;
+    bool wide = false;   // some prime is >= 2^30 (see WIDE_Q)
     pir::ModQ mod[PIR_MAX_PRIMES]{};
     pir::DbLayoutValu valu;
     pir::DbLayoutMfma mfma;

@@ -1,4 +1,5 @@
-// Device-side modular arithmetic for primes q < 2^30.
+// Device-side modular arithmetic for primes q < 2^32 (the lazy and MFMA forms
+// need q < 2^30; the _w / wide forms cover 2^30 <= q < 2^32).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,12 +41,40 @@ __device__ __forceinline__ uint64_t lazy_fold(uint64_t x, const ModQ &m) {
     return x;
 }
 
-// Barrett reduction of any 64-bit value into [0, q):
+// Barrett reduction of any 64-bit value into [0, q) for any q < 2^32:
 // qhat = floor(x * mu / 2^64) is floor(x/q) or one less, so one correction.
 __device__ __forceinline__ uint32_t reduce64(uint64_t x, const ModQ &m) {
     uint64_t qh = __umul64hi(x, m.mu);
     uint64_t r = x - qh * (uint64_t)m.q;
     return (uint32_t)(r >= m.q ? r - m.q : r);
+}
+
+// (wraps * 2^64 + sum) mod q: wraps * (2^64 mod q) < 2^16 * 2^32 for up to
+// 2^16 products, so one more Barrett step after adding it to sum mod q.
+__device__ __forceinline__ uint32_t reduce_wide(uint64_t sum, uint32_t wraps, const ModQ &m) {
+    return reduce64((uint64_t)reduce64(sum, m) + (uint64_t)wraps * m.r64, m);
+}
+
+// ------------------------------------------------- wide primes (q >= 2^30)
+// For 2^30 <= q < 2^32 a product of residues reaches 2^64 and a sum of two
+// residues 2^33, so these forms keep 64-bit intermediates.
+__device__ __forceinline__ uint32_t add_mod_w(uint32_t a, uint32_t b, uint32_t q) {
+    const uint64_t s = (uint64_t)a + b;
+    return (uint32_t)(s >= q ? s - q : s);
+}
+
+// Shoup's product with its [0, 2q) intermediate held in 64 bits.
+__device__ __forceinline__ uint32_t mul_shoup_w(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
+    const uint64_t r = (uint64_t)a * w - (uint64_t)__umulhi(a, ws) * q;
+    return (uint32_t)(r >= q ? r - q : r);
+}
+
+// A multiply-add keeps a 64-bit sum and counts its wraps (at most one per
+// product); the value is wraps * 2^64 + sum.
+__device__ __forceinline__ void mad_wide(uint64_t &sum, uint32_t &wraps, uint32_t x, uint32_t y) {
+    uint64_t t;
+    wraps += __builtin_add_overflow(sum, (uint64_t)x * y, &t) ? 1u : 0u;
+    sum = t;
 }
 
 // Shoup multiplication by a constant w < q with companion ws = floor(w*2^32/q):

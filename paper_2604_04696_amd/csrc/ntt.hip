@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -100,7 +101,8 @@ const NttTables &ntt_tables(uint32_t q, uint32_t n) {
 // ------------------------------------------------------------------ kernels
 constexpr int NTT_THREADS = 512;
 
-template <bool INV>
+// WIDE: q >= 2^30, sums and Shoup products kept in 64 bits (modarith.h).
+template <bool INV, bool WIDE>
 __global__ void __launch_bounds__(NTT_THREADS)
 ntt_kernel(const uint32_t *in, uint32_t *out, uint64_t in_stride,   // in may equal out
            uint64_t out_stride, const uint32_t *__restrict__ tw, uint32_t q, uint32_t n,
@@ -110,6 +112,10 @@ ntt_kernel(const uint32_t *in, uint32_t *out, uint64_t in_stride,   // in may eq
     uint32_t *dst = out + (uint64_t)blockIdx.x * out_stride;
     const uint32_t *tws = tw + n;
     const uint32_t tid = threadIdx.x;
+    auto addm = [](uint32_t a, uint32_t b, uint32_t qq) { return WIDE ? add_mod_w(a, b, qq) : add_mod(a, b, qq); };
+    auto mulm = [](uint32_t a, uint32_t w, uint32_t ws, uint32_t qq) {
+        return WIDE ? mul_shoup_w(a, w, ws, qq) : mul_shoup(a, w, ws, qq);
+    };
 
     for (uint32_t i = tid; i < n; i += NTT_THREADS) {
         uint32_t v = src[i];
@@ -127,8 +133,8 @@ ntt_kernel(const uint32_t *in, uint32_t *out, uint64_t in_stride,   // in may eq
                 uint32_t j = (i << (lt + 1)) + (b & ((1u << lt) - 1));
                 uint32_t t = 1u << lt;
                 uint32_t u = s[j];
-                uint32_t v = mul_shoup(s[j + t], tw[m + i], tws[m + i], q);
-                s[j] = add_mod(u, v, q);
+                uint32_t v = mulm(s[j + t], tw[m + i], tws[m + i], q);
+                s[j] = addm(u, v, q);
                 s[j + t] = sub_mod(u, v, q);
             }
             __syncthreads();
@@ -141,12 +147,12 @@ ntt_kernel(const uint32_t *in, uint32_t *out, uint64_t in_stride,   // in may eq
                 uint32_t j = (i << (lt + 1)) + (b & ((1u << lt) - 1));
                 uint32_t t = 1u << lt;
                 uint32_t u = s[j], v = s[j + t];
-                s[j] = add_mod(u, v, q);
-                s[j + t] = mul_shoup(sub_mod(u, v, q), tw[m + i], tws[m + i], q);
+                s[j] = addm(u, v, q);
+                s[j + t] = mulm(sub_mod(u, v, q), tw[m + i], tws[m + i], q);
             }
             __syncthreads();
         }
-        for (uint32_t i = tid; i < n; i += NTT_THREADS) dst[i] = mul_shoup(s[i], ninv, ninv_s, q);
+        for (uint32_t i = tid; i < n; i += NTT_THREADS) dst[i] = mulm(s[i], ninv, ninv_s, q);
     }
 }
 
@@ -159,14 +165,20 @@ void launch_ntt(const uint32_t *in, uint32_t *out, uint64_t count, uint64_t in_s
     // gridDim.x is limited to 2^31-1; count stays far below in practice
     for (uint64_t c0 = 0; c0 < count; c0 += (1u << 30)) {
         uint32_t c = (uint32_t)std::min<uint64_t>(count - c0, 1u << 30);
-        if (inverse)
-            ntt_kernel<true><<<c, NTT_THREADS, lds, st>>>(in + c0 * in_stride, out + c0 * out_stride,
-                                                          in_stride, out_stride, t.inv, t.q, t.n, logn,
-                                                          t.n_inv, t.n_inv_shoup);
-        else
-            ntt_kernel<false><<<c, NTT_THREADS, lds, st>>>(in + c0 * in_stride, out + c0 * out_stride,
-                                                           in_stride, out_stride, t.fwd, t.q, t.n, logn,
-                                                           0, 0);
+        auto go = [&](auto inv, auto wide) {
+            constexpr bool I = decltype(inv)::value, W = decltype(wide)::value;
+            ntt_kernel<I, W><<<c, NTT_THREADS, lds, st>>>(in + c0 * in_stride, out + c0 * out_stride, in_stride,
+                                                          out_stride, I ? t.inv : t.fwd, t.q, t.n, logn,
+                                                          I ? t.n_inv : 0, I ? t.n_inv_shoup : 0);
+        };
+        const bool wide = t.q >= WIDE_Q;
+        if (inverse) {
+            if (wide) go(std::true_type{}, std::true_type{});
+            else go(std::true_type{}, std::false_type{});
+        } else {
+            if (wide) go(std::false_type{}, std::true_type{});
+            else go(std::false_type{}, std::false_type{});
+        }
         PIR_LAUNCH_CHECK();
     }
 }

@@ -25,6 +25,8 @@
 // One pass cannot write whole plane rows: a row needs the same point of all
 // the 64 k of a chunk, i.e. 64 full polynomials (1 MiB at N = 4096) in one
 // block.
+#include <type_traits>
+
 #include "common.h"
 #include "mfma.h"
 #include "modarith.h"
@@ -43,7 +45,7 @@ struct QfPrimes {
 // Polynomials per block at ring dimension n (a power of two, 8 <= n <= 16384).
 static uint32_t qf_group(uint32_t n) { return std::min<uint32_t>(8, QF_LDS_WORDS / n); }
 
-template <int KG>
+template <int KG, bool WIDE>
 __global__ void __launch_bounds__(QF_THREADS)
 query_ntt_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint32_t d0, uint32_t L,
                  uint32_t n, uint32_t logn, QfPrimes pr) {
@@ -75,8 +77,9 @@ query_ntt_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint
             const uint32_t j = (i << (lt + 1)) + (bb & ((1u << lt) - 1));
             uint32_t *poly = s + kk * n;
             const uint32_t u = poly[j];
-            const uint32_t v = mul_shoup(poly[j + (1u << lt)], tw[mm + i], tws[mm + i], qv);
-            poly[j] = add_mod(u, v, qv);
+            const uint32_t v = WIDE ? mul_shoup_w(poly[j + (1u << lt)], tw[mm + i], tws[mm + i], qv)
+                                    : mul_shoup(poly[j + (1u << lt)], tw[mm + i], tws[mm + i], qv);
+            poly[j] = WIDE ? add_mod_w(u, v, qv) : add_mod(u, v, qv);
             poly[j + (1u << lt)] = sub_mod(u, v, qv);
         }
         __syncthreads();
@@ -130,7 +133,7 @@ __device__ __forceinline__ uint32_t qf_elem(uint32_t t, uint32_t r, uint32_t lo)
     return (t & ((1u << lo) - 1)) | (r << lo) | ((t >> lo) << (lo + 4));
 }
 
-template <int LOGN>
+template <int LOGN, bool WIDE>
 __global__ void __launch_bounds__(QF_THREADS)
 query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint32_t d0, uint32_t L,
                      uint32_t ppb, QfPrimes pr) {
@@ -161,7 +164,12 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
             const uint32_t x = q[off + qf_elem(t, r, lo)];
-            v[r] = x - __umulhi(x, r1) * qv;
+            if (WIDE) {   // q >= 2^30: [0, 2q) needs 64 bits; reduce fully (no lazy range)
+                const uint64_t y = (uint64_t)x - (uint64_t)__umulhi(x, r1) * qv;
+                v[r] = (uint32_t)(y >= qv ? y - qv : y);
+            } else {
+                v[r] = x - __umulhi(x, r1) * qv;
+            }
         }
     }
 #pragma unroll
@@ -190,7 +198,13 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
                     if (r & bit) continue;
                     const uint32_t e = qf_elem(t, r, lo);
                     const uint32_t gi = mgroups + (e >> (x + 1));
-                    qf_bfly(v[r], v[r | bit], tw[gi], tws[gi], qv, 2 * qv);
+                    if (WIDE) {   // canonical butterflies with 64-bit intermediates
+                        const uint32_t u = v[r], w = mul_shoup_w(v[r | bit], tw[gi], tws[gi], qv);
+                        v[r] = add_mod_w(u, w, qv);
+                        v[r | bit] = sub_mod(u, w, qv);
+                    } else {
+                        qf_bfly(v[r], v[r | bit], tw[gi], tws[gi], qv, 2 * qv);
+                    }
                 }
             }
         }
@@ -201,7 +215,7 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
     if (live) {
 #pragma unroll
         for (int r = 0; r < QR; ++r)
-            poly[qf_pad(__brev(qf_elem(t, r, lo)) >> (32 - logn))] = qf_reduce4(v[r], qv, 2 * qv);
+            poly[qf_pad(__brev(qf_elem(t, r, lo)) >> (32 - logn))] = WIDE ? v[r] : qf_reduce4(v[r], qv, 2 * qv);
     }
     __syncthreads();
     if (live) {
@@ -239,40 +253,35 @@ void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uin
             qf_attr(reinterpret_cast<const void *>(kern), lds);
             kern<<<(uint32_t)blocks, threads, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, ppb, pr);
         };
-        switch (logn) {
-            case 8: go(&query_ntt_reg_kernel<8>); break;
-            case 9: go(&query_ntt_reg_kernel<9>); break;
-            case 10: go(&query_ntt_reg_kernel<10>); break;
-            case 11: go(&query_ntt_reg_kernel<11>); break;
-            case 12: go(&query_ntt_reg_kernel<12>); break;
-            case 13: go(&query_ntt_reg_kernel<13>); break;
-            case 14: go(&query_ntt_reg_kernel<14>); break;
-            default: PIR_FAIL(PIR_EINVAL, "unsupported ring dimension %u", p.n);
-        }
+        auto pick = [&](auto wide) {
+            constexpr bool W = decltype(wide)::value;
+            switch (logn) {
+                case 8: go(&query_ntt_reg_kernel<8, W>); break;
+                case 9: go(&query_ntt_reg_kernel<9, W>); break;
+                case 10: go(&query_ntt_reg_kernel<10, W>); break;
+                case 11: go(&query_ntt_reg_kernel<11, W>); break;
+                case 12: go(&query_ntt_reg_kernel<12, W>); break;
+                case 13: go(&query_ntt_reg_kernel<13, W>); break;
+                case 14: go(&query_ntt_reg_kernel<14, W>); break;
+                default: PIR_FAIL(PIR_EINVAL, "unsupported ring dimension %u", p.n);
+            }
+        };
+        if (db.wide) pick(std::true_type{});
+        else pick(std::false_type{});
         PIR_LAUNCH_CHECK();
         return;
     }
     const uint64_t blocks = 2ull * B * p.nprimes * ((p.d0 + kgs - 1) / kgs);
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "query front-end launch too large");
     const size_t lds = (size_t)kgs * p.n * sizeof(uint32_t);
-    switch (kgs) {
-        case 8:
-            qf_attr(reinterpret_cast<const void *>(&query_ntt_kernel<8>), lds);
-            query_ntt_kernel<8><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n,
-                                                                           logn, pr);
-            break;
-        case 4:
-            qf_attr(reinterpret_cast<const void *>(&query_ntt_kernel<4>), lds);
-            query_ntt_kernel<4><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n,
-                                                                           logn, pr);
-            break;
-        case 2:
-            qf_attr(reinterpret_cast<const void *>(&query_ntt_kernel<2>), lds);
-            query_ntt_kernel<2><<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n,
-                                                                           logn, pr);
-            break;
-        default: PIR_FAIL(PIR_EINVAL, "unsupported ring dimension %u", p.n);
-    }
+    // small rings (N < 256): at most 32 KiB of polynomials per block, KG = 8
+    if (kgs != 8) PIR_FAIL(PIR_EINVAL, "unsupported ring dimension %u", p.n);
+    auto small = [&](auto kern) {
+        qf_attr(reinterpret_cast<const void *>(kern), lds);
+        kern<<<(uint32_t)blocks, QF_THREADS, lds, st>>>(q_coeff, q_ntt, p.d0, p.nprimes, p.n, logn, pr);
+    };
+    if (db.wide) small(&query_ntt_kernel<8, true>);
+    else small(&query_ntt_kernel<8, false>);
     PIR_LAUNCH_CHECK();
 }
 

@@ -19,6 +19,8 @@
 // layout.  Storing into the boundary layout directly scatters one 16-byte
 // piece per lane over as many cache lines, and those partial-line writes,
 // interleaved with the DB stream, cost about a tenth of the kernel's time.
+#include <type_traits>
+
 #include "common.h"
 #include "modarith.h"
 
@@ -48,7 +50,9 @@ static_assert(STREAM_THREADS == VALU_STRIP, "a streaming block covers one DB str
 constexpr int STREAM_ROWS = 8;   // rows per load batch and per fold
 static_assert(STREAM_ROWS <= 15, "a 64-bit sum absorbs at most fifteen products between folds");
 
-template <int MB>
+// WIDE (some prime >= 2^30): products reach 2^64, so each sum counts its
+// wraps instead of being folded (mad_wide / reduce_wide in modarith.h).
+template <int MB, bool WIDE>
 __global__ void __launch_bounds__(STREAM_THREADS)
 rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ qry,
                      uint4 *__restrict__ stage, uint32_t d0, uint32_t d1, uint32_t L, uint32_t N,
@@ -70,16 +74,31 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
     const uint4 *qv = reinterpret_cast<const uint4 *>(qry + (uint64_t)l * N + 4 * g);
     const uint64_t kstride = (uint64_t)L * N / 4, mstride = (uint64_t)d0 * kstride;
     uint64_t acc[MB][4];
+    uint32_t wraps[MB][4];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc[i][s] = 0;
+        for (int s = 0; s < 4; ++s) {
+            acc[i][s] = 0;
+            wraps[i][s] = 0;
+        }
+    auto mad = [&](int i, const uint4 &qq, const uint4 &d) {
+        if (WIDE) {
+            mad_wide(acc[i][0], wraps[i][0], qq.x, d.x);
+            mad_wide(acc[i][1], wraps[i][1], qq.y, d.y);
+            mad_wide(acc[i][2], wraps[i][2], qq.z, d.z);
+            mad_wide(acc[i][3], wraps[i][3], qq.w, d.w);
+        } else {
+            mad4s(acc[i], qq, d);
+        }
+    };
 
     auto load = [&](uint4 (&v)[STREAM_ROWS], uint32_t k) {
 #pragma unroll
         for (int u = 0; u < STREAM_ROWS; ++u) v[u] = ld_nt(dcol + (uint64_t)(k + u) * w);
     };
     auto fold_all = [&]() {
+        if (WIDE) return;
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -89,7 +108,7 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
 #pragma unroll
         for (int u = 0; u < STREAM_ROWS; ++u)
 #pragma unroll
-            for (int i = 0; i < MB; ++i) mad4s(acc[i], qv[i * mstride + (k + u) * kstride], v[u]);
+            for (int i = 0; i < MB; ++i) mad(i, qv[i * mstride + (k + u) * kstride], v[u]);
         fold_all();
     };
 
@@ -111,17 +130,24 @@ rowsel_stream_kernel(const uint4 *__restrict__ db, const uint32_t *__restrict__ 
         for (uint32_t k = k0; k < d0; ++k) {
             const uint4 v = ld_nt(dcol + (uint64_t)k * w);
 #pragma unroll
-            for (int i = 0; i < MB; ++i) mad4s(acc[i], qv[i * mstride + k * kstride], v);
+            for (int i = 0; i < MB; ++i) mad(i, qv[i * mstride + k * kstride], v);
         }
         fold_all();
     }
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         uint4 r;
-        r.x = reduce64(acc[i][0], mq);
-        r.y = reduce64(acc[i][1], mq);
-        r.z = reduce64(acc[i][2], mq);
-        r.w = reduce64(acc[i][3], mq);
+        if (WIDE) {
+            r.x = reduce_wide(acc[i][0], wraps[i][0], mq);
+            r.y = reduce_wide(acc[i][1], wraps[i][1], mq);
+            r.z = reduce_wide(acc[i][2], wraps[i][2], mq);
+            r.w = reduce_wide(acc[i][3], wraps[i][3], mq);
+        } else {
+            r.x = reduce64(acc[i][0], mq);
+            r.y = reduce64(acc[i][1], mq);
+            r.z = reduce64(acc[i][2], mq);
+            r.w = reduce64(acc[i][3], mq);
+        }
         st_nt(stage + ((uint64_t)gg * MB + i) * d1 + n, r);
     }
 }
@@ -171,13 +197,18 @@ void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint3
     {
         KernelTimer::Scope timed(st);
         dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
-        switch (m_rows) {
-            case 2: rowsel_stream_kernel<2><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-            case 4: rowsel_stream_kernel<4><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-            case 6: rowsel_stream_kernel<6><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-            case 8: rowsel_stream_kernel<8><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-            default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
-        }
+        auto go = [&](auto wide) {
+            constexpr bool W = decltype(wide)::value;
+            switch (m_rows) {
+                case 2: rowsel_stream_kernel<2, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                case 4: rowsel_stream_kernel<4, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                case 6: rowsel_stream_kernel<6, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                case 8: rowsel_stream_kernel<8, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
+            }
+        };
+        if (db.wide) go(std::true_type{});
+        else go(std::false_type{});
         PIR_LAUNCH_CHECK();
     }
     stream_out_transpose_kernel<<<(uint32_t)tblocks, 256, 0, st>>>(stage, reinterpret_cast<uint4 *>(out), groups, C,

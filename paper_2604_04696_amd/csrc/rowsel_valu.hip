@@ -84,6 +84,9 @@ constexpr int BM = 16 * TM, BN = 16 * TN;
 constexpr int TKC = 30;                   // rows per LDS step (two lazy groups)
 static_assert(VALU_STRIP % BN == 0, "a tiled block's columns lie in one DB strip");
 
+// WIDE (some prime >= 2^30): each sum counts its 64-bit wraps instead of
+// being folded (mad_wide / reduce_wide in modarith.h).
+template <bool WIDE>
 __global__ void __launch_bounds__(TILE_THREADS)
 rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint4 *__restrict__ qv,
                     uint32_t *__restrict__ out, uint32_t m_rows, uint32_t mp, uint32_t d0, uint32_t d1,
@@ -107,12 +110,16 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint4 *__restrict__ qv,
     const uint4 *dgrp = db + valu_strip_base(gg, strip, d0, d1) + c0;
     const uint4 *qgrp = qv + (uint64_t)gg * d0 * mp + m0;   // rows m0.. of this group, k-major
     uint64_t acc[TM][TN][4];
+    uint32_t wraps[TM][TN][4];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc[i][j][s] = 0;
+            for (int s = 0; s < 4; ++s) {
+                acc[i][j][s] = 0;
+                wraps[i][j][s] = 0;
+            }
 
     for (uint32_t k0 = 0; k0 < d0; k0 += TKC) {
         const uint32_t kc = min((uint32_t)TKC, d0 - k0);
@@ -143,14 +150,25 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint4 *__restrict__ qv,
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
-                    for (int j = 0; j < TN; ++j) mad4(acc[i][j], a[i], b[j]);
+                    for (int j = 0; j < TN; ++j) {
+                        if (WIDE) {
+                            mad_wide(acc[i][j][0], wraps[i][j][0], a[i].x, b[j].x);
+                            mad_wide(acc[i][j][1], wraps[i][j][1], a[i].y, b[j].y);
+                            mad_wide(acc[i][j][2], wraps[i][j][2], a[i].z, b[j].z);
+                            mad_wide(acc[i][j][3], wraps[i][j][3], a[i].w, b[j].w);
+                        } else {
+                            mad4(acc[i][j], a[i], b[j]);
+                        }
+                    }
             }
+            if (!WIDE) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
+                    for (int j = 0; j < TN; ++j)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[i][j][s] = lazy_fold(acc[i][j][s], mq);
+                        for (int s = 0; s < 4; ++s) acc[i][j][s] = lazy_fold(acc[i][j][s], mq);
+            }
         }
     }
 #pragma unroll
@@ -162,10 +180,17 @@ rowsel_tiled_kernel(const uint4 *__restrict__ db, const uint4 *__restrict__ qv,
             const uint32_t n = n0 + tn + 16 * j;
             if (n >= d1) continue;
             uint4 r;
-            r.x = reduce64(acc[i][j][0], mq);
-            r.y = reduce64(acc[i][j][1], mq);
-            r.z = reduce64(acc[i][j][2], mq);
-            r.w = reduce64(acc[i][j][3], mq);
+            if (WIDE) {
+                r.x = reduce_wide(acc[i][j][0], wraps[i][j][0], mq);
+                r.y = reduce_wide(acc[i][j][1], wraps[i][j][1], mq);
+                r.z = reduce_wide(acc[i][j][2], wraps[i][j][2], mq);
+                r.w = reduce_wide(acc[i][j][3], wraps[i][j][3], mq);
+            } else {
+                r.x = reduce64(acc[i][j][0], mq);
+                r.y = reduce64(acc[i][j][1], mq);
+                r.z = reduce64(acc[i][j][2], mq);
+                r.w = reduce64(acc[i][j][3], mq);
+            }
             *reinterpret_cast<uint4 *>(out + (((uint64_t)m * d1 + n) * L + l) * N + 4 * g) = r;
         }
     }
@@ -202,8 +227,12 @@ void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
                                                              p.d0, (uint32_t)groups, nkb, ngb);
         PIR_LAUNCH_CHECK();
         KernelTimer::Scope timed(st);
-        rowsel_tiled_kernel<<<(uint32_t)blocks, TILE_THREADS, 0, st>>>(
-            dbv, qv, out, m_rows, mp, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
+        if (db.wide)
+            rowsel_tiled_kernel<true><<<(uint32_t)blocks, TILE_THREADS, 0, st>>>(
+                dbv, qv, out, m_rows, mp, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
+        else
+            rowsel_tiled_kernel<false><<<(uint32_t)blocks, TILE_THREADS, 0, st>>>(
+                dbv, qv, out, m_rows, mp, p.d0, p.d1, p.nprimes, p.n, nblk_m, nblk_n, mods);
         PIR_LAUNCH_CHECK();
         return;
     }

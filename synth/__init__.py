@@ -201,6 +201,9 @@ PRIMES_N4096 = (1073692673, 1073668097)
 # 2^108 -- here the four largest 27-bit primes with q = 1 (mod 8192), product
 # 2^107.99 (checked the same way as the table above).
 PRIMES_Q108 = (134176769, 134111233, 134012929, 133963777)
+# Full 32-bit primes (products of residues reach 2^64): the two largest with
+# q = 1 (mod 8192).
+PRIMES_W32 = (4294828033, 4294729729)
 
 
 @dataclass(frozen=True)

@@ -62,7 +62,6 @@ def _create(params, layouts=pir.PIR_LAYOUT_VALU):
     (32768, [1073707009], 16, 16, "power of two"),
     (1024, [1073707009 - 2048], 16, 16, "not prime"),          # 1 mod 2048 but composite
     (1024, [1073707011], 16, 16, "not 1 mod"),
-    (1024, [(1 << 30) + 2049], 16, 16, "below 2^30"),
     (1024, [], 16, 16, "nprimes"),
     (1024, [1073707009] * 5, 16, 16, "nprimes"),
     (1024, [1073707009], 0, 16, "d0"),
@@ -77,6 +76,17 @@ def test_create_rejects_bad_params(L, n, primes, d0, d1, frag):
     st, msg = _create(p)
     assert st == pir.PIR_EINVAL, msg
     assert frag in msg
+
+
+def test_wide_prime_rejects_mfma_layout():
+    # a 32-bit prime (products up to 2^64) is served by the VALU layout only
+    p = pir.pir_params()
+    p.n, p.nprimes, p.d0, p.d1 = 4096, 1, 16, 16
+    p.q[0] = 4294828033
+    st, msg = _create(p, pir.PIR_LAYOUT_MFMA)
+    assert st == pir.PIR_EUNSUPPORTED and "below 2^30" in msg
+    st, msg = _create(p, pir.PIR_LAYOUT_VALU | pir.PIR_LAYOUT_MFMA)
+    assert st == pir.PIR_EUNSUPPORTED
 
 
 def test_composite_fixture_is_composite():

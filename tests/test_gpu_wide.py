@@ -1,0 +1,115 @@
+"""GPU parity with full 32-bit primes (2^30 <= q < 2^32; products of
+residues reach 2^64): the VALU path keeps 64-bit sums that count their
+wraps, the NTTs keep 64-bit intermediates, and the MFMA layout is refused.
+Against the CPU oracle word for word (tolerance 0)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import empty_u32, np_u32, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+W32 = synth.PRIMES_W32
+
+
+@pytest.fixture(scope="module")
+def pir():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_04696_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+SHAPES = [
+    # (N, primes, D0, D1, B): streaming kernel (2B <= 8) and tiled kernel
+    (64, W32, 37, 300, 1),
+    (64, W32, 100, 70, 3),
+    (64, (W32[0],), 20, 9, 4),
+    (32, W32, 130, 33, 9),
+    (4096, W32, 9, 5, 2),
+    # a wide prime next to a 30-bit one
+    (64, (W32[1], 1073692673), 45, 20, 5),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"N{s[0]}L{len(s[1])}_{s[2]}x{s[3]}_B{s[4]}" for s in SHAPES])
+def test_wide_rowsel_matches_oracle(pir, shape):
+    n, primes, d0, d1, B = shape
+    say("wide rowsel", shape)
+    coeffs = synth.db_coeffs(80, d0, d1, len(primes), n)
+    query = synth.query_uniform(81, B, d0, primes, n)
+    want = oracle.rowsel(query, oracle.ntt_db(coeffs, primes), primes)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_VALU)
+    pir.pir_db_load_ntt(db, to_dev(coeffs), domain=pir.PIR_DOMAIN_COEFF)
+    out = empty_u32(want.size)
+    out.fill_(-1)
+    pir.pir_rowsel(db, to_dev(query), out, pir.PIR_PATH_AUTO)
+    torch.cuda.synchronize()
+    got = np_u32(out).reshape(want.shape)
+    assert np.array_equal(got, want), f"{(got != want).sum()} of {want.size} words differ"
+
+
+@pytest.mark.parametrize("B", [2, 5])
+def test_wide_all_q_minus_one(pir, B):
+    # (q-1)^2 = 1 mod q with (q-1)^2 just below 2^64: almost every product
+    # wraps the 64-bit sum; every output must be D0 mod q
+    n, primes, d0, d1 = 16, W32, 4100, 6
+    say("wide q-1, B", B)
+    dhat = np.empty((d0, d1, len(primes), n), dtype=np.uint32)
+    qv = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
+    for l, q in enumerate(primes):
+        dhat[..., l, :] = q - 1
+        qv[..., l, :] = q - 1
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_VALU)
+    pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+    out = empty_u32(B * 2 * d1 * len(primes) * n)
+    pir.pir_rowsel(db, to_dev(qv), out, pir.PIR_PATH_VALU)
+    torch.cuda.synchronize()
+    want = np.array([d0 % q for q in primes], dtype=np.uint32)
+    assert np.all(np_u32(out).reshape(B, 2, d1, len(primes), n) == want[:, None])
+
+
+@pytest.mark.parametrize("q,n", [(W32[0], 4096), (W32[1], 64)])
+def test_wide_ntt_helper_matches_oracle(pir, q, n):
+    say("wide ntt", q, n)
+    a = synth.uniform_mod(synth.stream_key(82, synth.TAG_QUERY), np.arange(3 * n), q).reshape(3, n)
+    want = oracle.ntt_forward(a, q)
+    out = empty_u32(a.size)
+    pir.pir_ntt_forward(to_dev(a), out, n, q)
+    back = empty_u32(a.size)
+    pir.pir_ntt_inverse(out, back, n, q)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_u32(out).reshape(a.shape), want)
+    assert np.array_equal(np_u32(back).reshape(a.shape), a)
+
+
+@pytest.mark.parametrize("n", [64, 4096])
+def test_wide_coeff_query_matches_oracle(pir, n):
+    # the coefficient-domain front end: small-ring and register-blocked transforms
+    primes, d0, d1, B = W32, 21, 7, 3
+    say("wide rowsel_coeff N", n)
+    coeffs = synth.db_coeffs(83, d0, d1, len(primes), n)
+    w = synth.draw(synth.stream_key(84, synth.TAG_QUERY, 7), np.arange(B * 2 * d0 * len(primes) * n,
+                                                                        dtype=np.uint64))
+    qc = (w & np.uint64(0xFFFFFFFF)).astype(np.uint32).reshape(B, 2, d0, len(primes), n)
+    want = oracle.rowsel(oracle.ntt_db(qc, primes), oracle.ntt_db(coeffs, primes), primes)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_VALU)
+    pir.pir_db_load_ntt(db, to_dev(coeffs), domain=pir.PIR_DOMAIN_COEFF)
+    out = empty_u32(want.size)
+    pir.pir_rowsel_coeff(db, to_dev(qc), out, pir.PIR_PATH_AUTO)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_u32(out).reshape(want.shape), want)
+
+
+def test_wide_refuses_mfma(pir):
+    with pytest.raises(pir.PirError, match="below 2"):
+        pir.pir_db_create(pir.make_params(64, W32, 8, 8))

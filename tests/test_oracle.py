@@ -46,7 +46,8 @@ def _trial_prime(n):
 
 @pytest.mark.parametrize("n,bits,count,table", [(1024, 30, 1, synth.PRIME_N1024),
                                                 (4096, 30, 2, synth.PRIMES_N4096),
-                                                (4096, 27, 4, synth.PRIMES_Q108)])
+                                                (4096, 27, 4, synth.PRIMES_Q108),
+                                                (4096, 32, 2, synth.PRIMES_W32)])
 def test_primes_are_largest_ntt_friendly(n, bits, count, table):
     got = oracle.ntt_primes(n, bits, count)
     assert tuple(got) == tuple(table)
@@ -110,7 +111,8 @@ def test_ntt_matches_direct_evaluation(n):
     assert oracle.ntt_forward(a, q, psi).tolist() == _direct_ntt(a, q, psi)
 
 
-@pytest.mark.parametrize("q,n", [(1073707009, 1024), (1073692673, 4096), (133963777, 4096)])
+@pytest.mark.parametrize("q,n", [(1073707009, 1024), (1073692673, 4096), (133963777, 4096),
+                                 (4294828033, 4096), (4294729729, 64)])
 def test_ntt_matches_direct_evaluation_sampled(q, n):
     psi = oracle.psi(q, n)
     a = synth.uniform_mod(synth.stream_key(12, synth.TAG_QUERY), np.arange(n), q)
@@ -182,21 +184,24 @@ def _rand(seed, shape, primes, tag=synth.TAG_QUERY):
 P2 = synth.PRIMES_N4096
 
 
-def test_rowsel_matches_bigint_matmul():
-    Q = _rand(21, (3, 2, 5, 2, 8), P2)
-    D = _rand(22, (5, 4, 2, 8), P2, synth.TAG_DB)
-    assert np.array_equal(oracle.rowsel(Q, D, P2), _bigint_rowsel(Q, D, P2))
+@pytest.mark.parametrize("primes", [P2, synth.PRIMES_W32], ids=["30bit", "32bit"])
+def test_rowsel_matches_bigint_matmul(primes):
+    Q = _rand(21, (3, 2, 5, 2, 8), primes)
+    D = _rand(22, (5, 4, 2, 8), primes, synth.TAG_DB)
+    assert np.array_equal(oracle.rowsel(Q, D, primes), _bigint_rowsel(Q, D, primes))
 
 
-def test_rowsel_all_q_minus_one_is_d0():
-    # (q-1)^2 = 1 mod q, so every output is D0 mod q
+@pytest.mark.parametrize("primes", [P2, synth.PRIMES_W32], ids=["30bit", "32bit"])
+def test_rowsel_all_q_minus_one_is_d0(primes):
+    # (q-1)^2 = 1 mod q, so every output is D0 mod q (with 32-bit primes the
+    # products are just below 2^64 and their sums far above)
     d0, d1, n = 37, 3, 16
     Q = np.empty((2, 2, d0, 2, n), dtype=np.uint32)
     D = np.empty((d0, d1, 2, n), dtype=np.uint32)
-    for l, q in enumerate(P2):
+    for l, q in enumerate(primes):
         Q[..., l, :] = q - 1
         D[..., l, :] = q - 1
-    out = oracle.rowsel(Q, D, P2)
+    out = oracle.rowsel(Q, D, primes)
     assert np.all(out == d0)
 
 
