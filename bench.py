@@ -272,6 +272,30 @@ def q108_section(pir):
     return res
 
 
+def w32_section(pir):
+    """Two full 32-bit primes (products of residues up to 2^64) on the
+    headline shape (N = 4096, 512 x 512, 8 GiB, VALU layout): 1 and 4 clients
+    on the streaming kernel, 32 on the tiled kernel, median of event-timed calls."""
+    import torch
+    import synth
+    w = synth.WIDE32
+    db = build_db(pir, w, pir.PIR_LAYOUT_VALU)
+    time.sleep(2.0)
+    res = {"workload": w.name, "primes": list(w.primes), "db_gib": w.db_bytes / 2**30}
+    for B, reps in ((1, 10), (2, 5), (4, 5), (32, 3)):
+        q = make_query(pir, w, B, w.seed)
+        out = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
+        fn = lambda: pir.pir_rowsel(db, q, out, pir.PIR_PATH_VALU)
+        fn()
+        torch.cuda.synchronize()
+        ms = statistics.median(timed_calls(fn, reps))
+        res[f"b{B}_valu"] = {"ms": round(ms, 3), "db_gbs": round(w.db_bytes / (ms * 1e-3) / 1e9, 1),
+                             "mac_per_s": w.slots * 2 * B * w.d0 * w.d1 / (ms * 1e-3)}
+        del q, out
+    pir.pir_db_free(db)
+    return res
+
+
 def make_query_sub(pir, w, sub):
     import torch
     import synth
@@ -449,6 +473,9 @@ def main():
         line["q108"] = q108_section(pir)
         torch.cuda.empty_cache()
         log(f"four-limb setting: {line['q108']}")
+        line["w32"] = w32_section(pir)
+        torch.cuda.empty_cache()
+        log(f"32-bit primes: {line['w32']}")
 
     if not args.no_grouped:
         log("grouped instances")

@@ -180,40 +180,51 @@ stream_out_transpose_kernel(const uint4 *__restrict__ stage, uint4 *__restrict__
 
 void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, hipStream_t st) {
     const auto &p = db.p;
-    const uint32_t m_rows = 2 * B;
     const uint64_t groups = (uint64_t)p.nprimes * (p.n / 4);
     ModQ4s mods{};
     for (uint32_t l = 0; l < p.nprimes; ++l) mods.m[l] = db.mod[l];
     const uint4 *dbv = reinterpret_cast<const uint4 *>(db.valu.data);
     const uint32_t nblk_n = (p.d1 + STREAM_THREADS - 1) / STREAM_THREADS;
     const uint64_t blocks = groups * nblk_n;
-    const uint64_t C = (uint64_t)m_rows * p.d1;
+    // With 32-bit primes the kernel's registers grow with the rows it carries
+    // (two 64-bit words per sum), and beyond one client it runs at low
+    // occupancy: 4 clients in one pass took 15.6 ms on the 8 GiB DB, one pass
+    // per client 1.5 ms each.  So wide DBs take one pass per client, each
+    // re-reading the DB.
+    const uint32_t rows_per_pass = db.wide ? 2u : 2 * B;
+    const uint32_t passes = 2 * B / rows_per_pass;
+    const uint64_t C = (uint64_t)rows_per_pass * p.d1;
     const uint64_t nblk_c = (C + TR_C - 1) / TR_C;
     const uint64_t tblocks = nblk_c * ((groups + TR_G - 1) / TR_G);
     if (blocks >= (1ull << 31) || tblocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
 
-    StreamScratch scratch(groups * C * sizeof(uint4), st);   // [groups][2B][D1] vectors
+    StreamScratch scratch(groups * C * sizeof(uint4), st);   // [groups][rows][D1] vectors, reused per pass
     uint4 *stage = scratch.as<uint4>();
-    {
-        KernelTimer::Scope timed(st);
-        dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
-        auto go = [&](auto wide) {
-            constexpr bool W = decltype(wide)::value;
-            switch (m_rows) {
-                case 2: rowsel_stream_kernel<2, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-                case 4: rowsel_stream_kernel<4, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-                case 6: rowsel_stream_kernel<6, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-                case 8: rowsel_stream_kernel<8, W><<<grid, block, 0, st>>>(dbv, q, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
-                default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", m_rows);
-            }
-        };
-        if (db.wide) go(std::true_type{});
-        else go(std::false_type{});
+    const uint64_t q_rows = (uint64_t)p.d0 * p.nprimes * p.n, o_rows = (uint64_t)p.d1 * p.nprimes * p.n;
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+        const uint32_t *qp = q + pass * rows_per_pass * q_rows;
+        uint32_t *op = out + pass * rows_per_pass * o_rows;
+        {
+            KernelTimer::Scope timed(st);
+            dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
+            auto go = [&](auto wide) {
+                constexpr bool W = decltype(wide)::value;
+                switch (rows_per_pass) {
+                    case 2: rowsel_stream_kernel<2, W><<<grid, block, 0, st>>>(dbv, qp, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                    case 4: rowsel_stream_kernel<4, W><<<grid, block, 0, st>>>(dbv, qp, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                    case 6: rowsel_stream_kernel<6, W><<<grid, block, 0, st>>>(dbv, qp, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                    case 8: rowsel_stream_kernel<8, W><<<grid, block, 0, st>>>(dbv, qp, stage, p.d0, p.d1, p.nprimes, p.n, nblk_n, mods); break;
+                    default: PIR_FAIL(PIR_EINVAL, "unexpected row count %u", rows_per_pass);
+                }
+            };
+            if (db.wide) go(std::true_type{});
+            else go(std::false_type{});
+            PIR_LAUNCH_CHECK();
+        }
+        stream_out_transpose_kernel<<<(uint32_t)tblocks, 256, 0, st>>>(stage, reinterpret_cast<uint4 *>(op), groups,
+                                                                     C, (uint32_t)nblk_c);
         PIR_LAUNCH_CHECK();
     }
-    stream_out_transpose_kernel<<<(uint32_t)tblocks, 256, 0, st>>>(stage, reinterpret_cast<uint4 *>(out), groups, C,
-                                                                 (uint32_t)nblk_c);
-    PIR_LAUNCH_CHECK();
 }
 
 }  // namespace pir

@@ -252,6 +252,8 @@ BATCHED = Workload("rowsel_n4096_l2_512x512_b64", 3, 4096, PRIMES_N4096, 512, 51
                    "uniform", db_seed=2, note="same DB as the one-client case")
 SERVE_DB = Workload("serve_n4096_l2_1024x1024", 5, 4096, PRIMES_N4096, 1024, 1024, 1,
                     "uniform", note="32 GiB resident DB; requests drawn from a 32-query pool")
+WIDE32 = Workload("rowsel_n4096_l2w32_512x512_b1", 7, 4096, PRIMES_W32, 512, 512, 1, "uniform",
+                  note="two full 32-bit primes (products up to 2^64), 8 GiB DB, VALU layout")
 PAPER_Q108 = Workload("rowsel_n4096_l4q108_256x512_b32", 6, 4096, PRIMES_Q108, 256, 512, 32,
                       "uniform", note="four 27-bit limbs (Q ~ 2^108) and D0 = 256 as in the paper's "
                       "setting; 8 GiB DB; one client and a batch of 32")
