@@ -436,7 +436,7 @@ def main():
         "mac_per_s": w.macs / (ms_step * 1e-3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "rowsel_stream_kernel<2>", "kernel_ms": round(kmean, 4),
+                     "kernel": "rowsel_stream_kernel<2, false>", "kernel_ms": round(kmean, 4),
                      "call_ms": round(call_ms, 4),
                      "alg_bytes_per_launch": alg_bytes,
                      "measured_copy_gbs": round(copy_gbs, 1),
