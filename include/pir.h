@@ -62,11 +62,13 @@ typedef enum {
  *   nprimes L: number of RNS primes, 1..4 (the paper uses four, sec. 2.4.1)
  *   q[l]    primes with q = 1 (mod 2N) (needed for the negacyclic NTT), each
  *           a 32-bit word.  Below 2^30 the VALU kernels keep up to fifteen
- *           60-bit products in one 64-bit sum and the INT8 MFMA path applies;
- *           a DB with any prime of 2^30 or more (products up to 2^64, the
- *           paper's "32-bit primes", sec. 2.4.1) is served by the VALU layout
- *           only, with 64-bit sums that count their wraps: creating it with
- *           PIR_LAYOUT_MFMA fails with PIR_EUNSUPPORTED
+ *           60-bit products in one 64-bit sum.  With any prime of 2^30 or
+ *           more (products up to 2^64, the 32-bit primes of sec. 2.4.1) the
+ *           VALU kernels keep 64-bit sums that count their wraps and the INT8
+ *           MFMA path splits centred residues (-q/2, q/2] into four signed
+ *           digits, which reach primes up to 4278124286 (twice the largest
+ *           digit sum, 127 * (1 + 2^8 + 2^16 + 2^24)); creating a DB with a
+ *           larger prime and PIR_LAYOUT_MFMA fails with PIR_EUNSUPPORTED
  *   d0, d1  DB rows (selector count) and columns, each 1..65536 */
 typedef struct {
     uint32_t n;

@@ -7,9 +7,18 @@ namespace pir {
 
 // Per-prime constants of the epilogue.
 struct EpiQ {
-    double qd, qinv, c32, c47;
+    double qd, qinv, c32, c47, c48;   // q, 1/q, 2^32, 2^47 and 2^48 mod q in binary64
     uint32_t q, pad;
 };
+
+// Recombination variants of combine_classes (modarith.h): direct, split at
+// 2^15 (primes below 2^30 with a large 2^32 mod q), and wide (primes of
+// 2^30 or more: split at 2^16, 64-bit final conversion).
+enum : int { RECOMB_DIRECT = 0, RECOMB_SPLIT = 1, RECOMB_WIDE = 2 };
+
+// Largest prime whose centred residues (-q/2, q/2] four balanced signed
+// 8-bit digits can represent: the digits reach 127 * (1 + 2^8 + 2^16 + 2^24).
+constexpr uint32_t MFMA_MAX_Q = 4278124286u;
 
 // One RowSel instance on the MFMA path.  Its output tiles are numbered
 // [tile0, tile0 + tiles) in the launch's global tile order.
@@ -22,7 +31,7 @@ struct MfmaJob {
     uint32_t g_begin;      // first point group (groups of four points) of this job
     uint32_t wm;           // waves along m: 4 (128 x 64 tiles) or 2 (64 x 128 tiles)
     uint32_t nblk_m, nblk_n, groups, tile0, tiles;
-    uint32_t split;        // 1: some prime needs the split recombination (combine_classes)
+    uint32_t split;        // recombination variant of the job's primes (RECOMB_*)
     uint32_t sstride;      // staging row stride: d1 rounded up to a multiple of 4 (16-byte rows)
     EpiQ q[PIR_MAX_PRIMES];
 };

@@ -112,13 +112,19 @@ __device__ __forceinline__ double round_mul(double x, double s) {
 //   SPLIT = false:  t = E + h c32, exact when q c32 < 3 * 2^51 - 2^45 (the
 //                   host checks this; it holds for every q < 2^26 and for q
 //                   just below 2^30, where c32 = 4 (2^30 - q) is small);
-//   SPLIT = true:   h = 2^15 h1 + h0 (0 <= h0 < 2^15, |h1| <= 2^15) and
+//   MODE = 1:       h = 2^15 h1 + h0 (0 <= h0 < 2^15, |h1| <= 2^15) and
 //                   t = E + h0 c32 + h1 c47, c47 = 2^47 mod q, each product
 //                   below 2^45 in magnitude;
+//   MODE = 2 (any q up to MFMA_MAX_Q; taken when some prime is 2^30 or
+//             more; |h| <= q/2 < 2^31):
+//                   h = 2^16 h1 + h0 (0 <= h0 < 2^16, |h1| <= 2^15) and
+//                   t = E + h0 c32 + h1 c48, c48 = 2^48 mod q, products below
+//                   2^48, |t| < 2^52;
 // finally r = t - round(t/q) q lies in (-q, q) and min(r, r + q) taken as
-// unsigned 32-bit words is the canonical residue.  (M is any struct with
-// qd, qinv, c32, c47 and q.)
-template <bool SPLIT, class M>
+// unsigned 32-bit words is the canonical residue (for MODE 2, where q may
+// exceed 2^31, r goes through a 64-bit integer).  MODE = 0 is the direct
+// form above.  (M is any struct with qd, qinv, c32, c47, c48 and q.)
+template <int MODE, class M>
 __device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const M &m) {
     double e = (double)g[3];
     e = fma(e, 256.0, (double)g[2]);
@@ -129,7 +135,15 @@ __device__ __forceinline__ uint32_t combine_classes(const int (&g)[7], const M &
     hh = fma(hh, 256.0, (double)g[4]);
     const double h = fma(-round_mul(hh, m.qinv), m.qd, hh);
     double t;
-    if (SPLIT) {
+    if (MODE == 2) {
+        const double h1 = floor(h * (1.0 / 65536.0));
+        const double h0 = fma(-h1, 65536.0, h);
+        t = fma(h0, m.c32, e);
+        t = fma(h1, m.c48, t);
+        const int64_t r = (int64_t)fma(-round_mul(t, m.qinv), m.qd, t);
+        return (uint32_t)(r < 0 ? r + (int64_t)m.q : r);
+    }
+    if (MODE == 1) {
         const double h1 = floor(h * (1.0 / 32768.0));
         const double h0 = fma(-h1, 32768.0, h);
         t = fma(h0, m.c32, e);
@@ -147,8 +161,10 @@ __host__ __device__ inline bool combine_direct_ok(uint32_t q) {
     return (double)q * c32 <= 3.0 * 2251799813685248.0 - 35184372088832.0;   // 3*2^51 - 2^45
 }
 
-// Balanced signed base-2^8 digits of x < 2^31: x = sum_i d_i 2^(8i),
-// d_i in [-128, 127] (the top digit of x < 2^30 stays within [0, 64]).
+// Balanced signed base-2^8 digits of a 32-bit value read as signed,
+// -2155905152 <= x <= 2139062143: x = sum_i d_i 2^(8i), d_i in [-128, 127]
+// (the top digit of 0 <= x < 2^30 stays within [0, 64]; centred residues of
+// primes up to MFMA_MAX_Q are passed as negative values above q/2).
 // Returned packed as four int8 in one 32-bit word, digit i in byte i.
 __device__ __forceinline__ uint32_t split_digits(uint32_t x) {
     uint32_t packed = 0;

@@ -53,12 +53,20 @@ struct ModQ4m {
 // [klo, khi) and rows r >= r_valid read as zero; rows r >= R are not
 // written; 16-byte chunks that straddle [klo, khi) (only when loading a DB
 // in row ranges) are written byte by byte so neighbouring ranges are not
-// overwritten.
+// overwritten.  CENTER (DBs with a prime of 2^30 or more): a residue above
+// q_l/2 is taken as x - q_l first, so that four balanced digits cover it
+// (point p belongs to prime p / N).
+struct DigitCenter {
+    uint32_t q[PIR_MAX_PRIMES];
+    uint32_t n;
+};
+
+template <bool CENTER>
 __global__ void __launch_bounds__(256)
 digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k,
                     int8_t *__restrict__ dst, uint32_t R, uint32_t r_valid, uint32_t P,
                     uint32_t kp, uint32_t klo, uint32_t khi, uint32_t kvalid, uint32_t kblk0,
-                    uint32_t nkblk, uint32_t RS, uint32_t row0) {
+                    uint32_t nkblk, uint32_t RS, uint32_t row0, DigitCenter dc) {
     __shared__ uint32_t tile[2][64][65];
     const uint32_t tid = threadIdx.x;
     uint64_t b = blockIdx.x;
@@ -75,9 +83,13 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
     for (int j = 0; j < 32; ++j) {
         const uint32_t e = tid + 256 * j, rr = e / 4096, kk = (e / 64) % 64, pp = e % 64;
         const uint32_t k = k0 + kk, r = r0 + rr;
-        v[j] = r < r_valid && k >= klo && k < khi && p0 + pp < P
-                   ? __builtin_nontemporal_load(src + (uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp)
-                   : 0u;
+        const bool in = r < r_valid && k >= klo && k < khi && p0 + pp < P;
+        v[j] = in ? __builtin_nontemporal_load(src + (uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp)
+                  : 0u;
+        if (CENTER && in) {
+            const uint32_t qq = dc.q[(p0 + pp) / dc.n];
+            v[j] = v[j] > qq / 2 ? v[j] - qq : v[j];   // two's complement of the negative residue
+        }
     }
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
@@ -115,7 +127,7 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
     }
 }
 
-static void launch_digit_planes(const uint32_t *src, uint64_t s_r, uint64_t s_k, int8_t *dst,
+static void launch_digit_planes(const pir_db &db, const uint32_t *src, uint64_t s_r, uint64_t s_k, int8_t *dst,
                                 uint32_t R, uint32_t r_valid, uint32_t P, uint32_t kp,
                                 uint32_t klo, uint32_t khi, uint32_t kvalid, hipStream_t st,
                                 uint32_t RS = 0, uint32_t row0 = 0) {
@@ -127,8 +139,15 @@ static void launch_digit_planes(const uint32_t *src, uint64_t s_r, uint64_t s_k,
     const uint32_t nkb = kb1 - kb0;
     const uint64_t blocks = (uint64_t)((P + 63) / 64) * nkb * ((R + 1) / 2);
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "digit-plane launch too large");
-    digit_planes_kernel<<<(uint32_t)blocks, 256, 0, st>>>(src, s_r, s_k, dst, R, r_valid, P, kp, klo,
-                                                          khi, kvalid, kb0, nkb, RS, row0);
+    DigitCenter dc{};
+    for (uint32_t l = 0; l < db.p.nprimes; ++l) dc.q[l] = db.p.q[l];
+    dc.n = db.p.n;
+    if (db.wide)
+        digit_planes_kernel<true><<<(uint32_t)blocks, 256, 0, st>>>(src, s_r, s_k, dst, R, r_valid, P, kp, klo,
+                                                                    khi, kvalid, kb0, nkb, RS, row0, dc);
+    else
+        digit_planes_kernel<false><<<(uint32_t)blocks, 256, 0, st>>>(src, s_r, s_k, dst, R, r_valid, P, kp, klo,
+                                                                     khi, kvalid, kb0, nkb, RS, row0, dc);
     PIR_LAUNCH_CHECK();
 }
 
@@ -139,7 +158,7 @@ void launch_db_layout_mfma(const pir_db &db, const uint32_t *ntt_src, uint32_t r
     const auto &p = db.p;
     const uint32_t P = p.n * p.nprimes;
     // src index = (k - row0)*D1*P + n*P + point
-    launch_digit_planes(ntt_src, P, (uint64_t)p.d1 * P, db.mfma.data, p.d1, p.d1, P, db.mfma.kp,
+    launch_digit_planes(db, ntt_src, P, (uint64_t)p.d1 * P, db.mfma.data, p.d1, p.d1, P, db.mfma.kp,
                         row0, row0 + nrows, p.d0, st);
 }
 
@@ -309,7 +328,7 @@ struct LoadCursor {
 //
 // A single instance travels by value in `one` (ONE = true); a grouped launch
 // passes a device array of jobs sorted by tile0.
-template <bool ONE, int BM, bool SPLIT>
+template <bool ONE, int BM, int MODE>
 __global__ void __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint32_t njobs,
                        uint32_t total_tiles) {
@@ -454,8 +473,10 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
                 int gr[7];
 #pragma unroll
                 for (int c = 0; c < 7; ++c) gr[c] = acc[c][r];
-                const uint32_t part = combine_classes<SPLIT>(gr, mq);
-                res[r] = first ? part : add_mod(res[r], part, mq.q);
+                const uint32_t part = combine_classes<MODE>(gr, mq);
+                // a sum of two residues of a prime above 2^31 needs 33 bits
+                res[r] = first ? part : MODE == RECOMB_WIDE ? add_mod_w(res[r], part, mq.q)
+                                                            : add_mod(res[r], part, mq.q);
             }
 #pragma unroll
             for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
@@ -580,12 +601,14 @@ MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_
     j.nblk_n = (p.d1 + 32 * (NWAVE / wm) - 1) / (32 * (NWAVE / wm));
     j.tile0 = tile0;
     j.tiles = j.groups * j.nblk_m * j.nblk_n;
-    j.split = 0;
+    j.split = RECOMB_DIRECT;
     for (uint32_t l = 0; l < p.nprimes; ++l) {
         const ModQ &m = db.mod[l];
-        j.q[l] = EpiQ{m.qd, m.qinv, m.c32, m.c47, m.q, 0};
-        if (!combine_direct_ok(m.q)) j.split = 1;
+        const double c48 = (double)(uint32_t)((1ull << 48) % m.q);
+        j.q[l] = EpiQ{m.qd, m.qinv, m.c32, m.c47, c48, m.q, 0};
+        if (!combine_direct_ok(m.q)) j.split = std::max<uint32_t>(j.split, RECOMB_SPLIT);
     }
+    if (db.wide) j.split = RECOMB_WIDE;
     return j;
 }
 
@@ -606,23 +629,25 @@ void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njob
     const uint32_t grid = 8 * (uint32_t)std::max(1, cu_count() / 8);
     // every job of one launch shares the tile shape and the recombination
     // variant of `one`
-    auto go = [&](auto bm, auto split) {
+    auto go = [&](auto bm, auto mode) {
         constexpr int BM = decltype(bm)::value;
-        constexpr bool SPLIT = decltype(split)::value;
+        constexpr int MODE = decltype(mode)::value;
         if (jobs_dev)
-            rowsel_mfma_persistent<false, BM, SPLIT><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
+            rowsel_mfma_persistent<false, BM, MODE><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs, total_tiles);
         else
-            rowsel_mfma_persistent<true, BM, SPLIT><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+            rowsel_mfma_persistent<true, BM, MODE><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1, total_tiles);
+    };
+    auto go_mode = [&](auto bm) {
+        switch (one.split) {
+            case RECOMB_DIRECT: go(bm, std::integral_constant<int, RECOMB_DIRECT>{}); break;
+            case RECOMB_SPLIT: go(bm, std::integral_constant<int, RECOMB_SPLIT>{}); break;
+            default: go(bm, std::integral_constant<int, RECOMB_WIDE>{}); break;
+        }
     };
     using B64 = std::integral_constant<int, 64>;
     using B128 = std::integral_constant<int, 128>;
-    if (one.wm == 4) {
-        if (one.split) go(B128{}, std::true_type{});
-        else go(B128{}, std::false_type{});
-    } else {
-        if (one.split) go(B64{}, std::true_type{});
-        else go(B64{}, std::false_type{});
-    }
+    if (one.wm == 4) go_mode(B128{});
+    else go_mode(B64{});
     PIR_LAUNCH_CHECK();
 }
 
@@ -634,14 +659,14 @@ void launch_query_digits(const pir_db &db, const uint32_t *q, uint32_t B, int8_t
     const auto &p = db.p;
     const uint32_t P = p.n * p.nprimes;
     const uint32_t mp = (2 * B + 31) / 32 * 32;
-    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, 2 * B, 2 * B, P, db.mfma.kp, 0, p.d0, p.d0, st, mp);
+    launch_digit_planes(db, q, (uint64_t)p.d0 * P, P, qd, 2 * B, 2 * B, P, db.mfma.kp, 0, p.d0, p.d0, st, mp);
 }
 
 void launch_query_digits_rows(const pir_db &db, const uint32_t *q, uint32_t rows, int8_t *qd,
                               uint32_t mstride, uint32_t row0, hipStream_t st) {
     const auto &p = db.p;
     const uint32_t P = p.n * p.nprimes;
-    launch_digit_planes(q, (uint64_t)p.d0 * P, P, qd, rows, rows, P, db.mfma.kp, 0, p.d0, p.d0, st, mstride,
+    launch_digit_planes(db, q, (uint64_t)p.d0 * P, P, qd, rows, rows, P, db.mfma.kp, 0, p.d0, p.d0, st, mstride,
                         row0);
 }
 
@@ -791,9 +816,10 @@ static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t cou
             pl.jobs.push_back(j);
         }
         pl.total_tiles = tile0;
-        // one recombination variant per launch: the split one if any job needs it
-        uint32_t split = 0;
-        for (const MfmaJob &j : pl.jobs) split |= j.split;
+        // one recombination variant per launch: the widest any job needs (each
+        // variant is exact for the primes of the narrower ones)
+        uint32_t split = RECOMB_DIRECT;
+        for (const MfmaJob &j : pl.jobs) split = std::max(split, j.split);
         for (MfmaJob &j : pl.jobs) j.split = split;
         if (!pl.jobs.empty()) {
             PIR_HIP(hipMemcpyAsync(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(),

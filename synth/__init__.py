@@ -204,6 +204,12 @@ PRIMES_Q108 = (134176769, 134111233, 134012929, 133963777)
 # Full 32-bit primes (products of residues reach 2^64): the two largest with
 # q = 1 (mod 8192).
 PRIMES_W32 = (4294828033, 4294729729)
+# Wide primes the INT8 path can take once residues are centred to
+# (-q/2, q/2]: the two largest 31-bit ones, and the two largest 32-bit ones not
+# above 4278124286 (= 2 * 2139062143, the reach of four balanced 8-bit
+# digits), all with q = 1 (mod 8192).
+PRIMES_W31 = (2147377153, 2147352577)
+PRIMES_W32_MFMA = (4278108161, 4277690369)
 
 
 @dataclass(frozen=True)
@@ -254,6 +260,9 @@ SERVE_DB = Workload("serve_n4096_l2_1024x1024", 5, 4096, PRIMES_N4096, 1024, 102
                     "uniform", note="32 GiB resident DB; requests drawn from a 32-query pool")
 WIDE32 = Workload("rowsel_n4096_l2w32_512x512_b1", 7, 4096, PRIMES_W32, 512, 512, 1, "uniform",
                   note="two full 32-bit primes (products up to 2^64), 8 GiB DB, VALU layout")
+WIDE32_MFMA = Workload("rowsel_n4096_l2w32m_512x512_b32", 8, 4096, PRIMES_W32_MFMA, 512, 512, 32, "uniform",
+                       note="the two largest 32-bit primes the INT8 path takes (centred residues), "
+                            "8 GiB DB, both layouts, a batch of 32")
 PAPER_Q108 = Workload("rowsel_n4096_l4q108_256x512_b32", 6, 4096, PRIMES_Q108, 256, 512, 32,
                       "uniform", note="four 27-bit limbs (Q ~ 2^108) and D0 = 256 as in the paper's "
                       "setting; 8 GiB DB; one client and a batch of 32")

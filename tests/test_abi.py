@@ -79,12 +79,13 @@ def test_create_rejects_bad_params(L, n, primes, d0, d1, frag):
 
 
 def test_wide_prime_rejects_mfma_layout():
-    # a 32-bit prime (products up to 2^64) is served by the VALU layout only
+    # a prime above 4278124286 has centred residues beyond four signed 8-bit
+    # digits: the VALU layout only
     p = pir.pir_params()
     p.n, p.nprimes, p.d0, p.d1 = 4096, 1, 16, 16
     p.q[0] = 4294828033
     st, msg = _create(p, pir.PIR_LAYOUT_MFMA)
-    assert st == pir.PIR_EUNSUPPORTED and "below 2^30" in msg
+    assert st == pir.PIR_EUNSUPPORTED and "at most 4278124286" in msg
     st, msg = _create(p, pir.PIR_LAYOUT_VALU | pir.PIR_LAYOUT_MFMA)
     assert st == pir.PIR_EUNSUPPORTED
 

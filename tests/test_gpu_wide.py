@@ -1,7 +1,8 @@
-"""GPU parity with full 32-bit primes (2^30 <= q < 2^32; products of
-residues reach 2^64): the VALU path keeps 64-bit sums that count their
-wraps, the NTTs keep 64-bit intermediates, and the MFMA layout is refused.
-Against the CPU oracle word for word (tolerance 0)."""
+"""GPU parity with primes of 2^30 or more (products of residues reach 2^64):
+the VALU path keeps 64-bit sums that count their wraps, the NTTs keep 64-bit
+intermediates, and the INT8 MFMA path takes centred residues and the wide
+recombination for primes up to 4278124286 (refusing larger ones).  Against
+the CPU oracle word for word (tolerance 0)."""
 import numpy as np
 import pytest
 
@@ -113,3 +114,75 @@ def test_wide_coeff_query_matches_oracle(pir, n):
 def test_wide_refuses_mfma(pir):
     with pytest.raises(pir.PirError, match="below 2"):
         pir.pir_db_create(pir.make_params(64, W32, 8, 8))
+
+
+# ------------------------------------------------ INT8 MFMA path, centred digits
+W31, W32M = synth.PRIMES_W31, synth.PRIMES_W32_MFMA
+
+MFMA_SHAPES = [
+    # (N, primes, D0, D1, B): 64 x 128 tiles (2B <= 64) and 128 x 64 tiles
+    (64, W32M, 37, 40, 3),
+    (64, W31, 130, 33, 17),
+    (32, W32M, 100, 24, 40),
+    # a wide prime beside a 30-bit one (one launch, the wide recombination)
+    (16, (W32M[0], 1073692673), 70, 20, 9),
+    # D0 above the 2048-row int32 accumulation chunk
+    (16, W32M, 2100, 6, 2),
+]
+
+
+@pytest.mark.parametrize("shape", MFMA_SHAPES, ids=[f"N{s[0]}L{len(s[1])}_{s[2]}x{s[3]}_B{s[4]}"
+                                                     for s in MFMA_SHAPES])
+def test_wide_mfma_matches_oracle(pir, shape):
+    n, primes, d0, d1, B = shape
+    say("wide mfma", shape)
+    coeffs = synth.db_coeffs(85, d0, d1, len(primes), n)
+    query = synth.query_uniform(86, B, d0, primes, n)
+    want = oracle.rowsel(query, oracle.ntt_db(coeffs, primes), primes)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1))          # both layouts
+    pir.pir_db_load_ntt(db, to_dev(coeffs), domain=pir.PIR_DOMAIN_COEFF)
+    for path in (pir.PIR_PATH_MFMA_I8, pir.PIR_PATH_VALU):
+        out = empty_u32(want.size)
+        out.fill_(-1)
+        pir.pir_rowsel(db, to_dev(query), out, path)
+        torch.cuda.synchronize()
+        got = np_u32(out).reshape(want.shape)
+        assert np.array_equal(got, want), f"path {path}: {(got != want).sum()} of {want.size} words differ"
+
+
+def test_wide_mfma_extreme_centred_residues(pir):
+    # DB residues (q-1)/2 and queries (q+1)/2 (centred: +(q-1)/2 and -(q-1)/2,
+    # the largest magnitudes four digits must carry), D0 above one K chunk
+    n, primes, d0, d1, B = 16, W32M, 4100, 5, 2
+    say("wide mfma extremes")
+    dhat = np.empty((d0, d1, len(primes), n), dtype=np.uint32)
+    qv = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
+    for l, q in enumerate(primes):
+        dhat[..., l, :] = (q - 1) // 2
+        qv[..., l, :] = (q + 1) // 2
+    want = oracle.rowsel(qv, dhat, primes)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_MFMA)
+    pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+    out = empty_u32(want.size)
+    pir.pir_rowsel(db, to_dev(qv), out, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_u32(out).reshape(want.shape), want)
+
+
+def test_wide_mfma_grouped_with_narrow_instance(pir):
+    # one grouped launch over a wide and a 30-bit instance: the widest
+    # recombination serves both
+    specs = [(64, W31, 40, 24, 5), (64, synth.PRIMES_N4096, 70, 16, 20)]
+    items, wants = [], []
+    for i, (n, primes, d0, d1, B) in enumerate(specs):
+        coeffs = synth.db_coeffs(87 + i, d0, d1, len(primes), n)
+        query = synth.query_uniform(89 + i, B, d0, primes, n)
+        wants.append(oracle.rowsel(query, oracle.ntt_db(coeffs, primes), primes))
+        db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_MFMA)
+        pir.pir_db_load_ntt(db, to_dev(coeffs), domain=pir.PIR_DOMAIN_COEFF)
+        items.append((db, to_dev(query), B, empty_u32(wants[-1].size)))
+    say("wide grouped")
+    pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    for (db, q, B, out), want in zip(items, wants):
+        assert np.array_equal(np_u32(out).reshape(want.shape), want)

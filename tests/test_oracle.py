@@ -47,7 +47,8 @@ def _trial_prime(n):
 @pytest.mark.parametrize("n,bits,count,table", [(1024, 30, 1, synth.PRIME_N1024),
                                                 (4096, 30, 2, synth.PRIMES_N4096),
                                                 (4096, 27, 4, synth.PRIMES_Q108),
-                                                (4096, 32, 2, synth.PRIMES_W32)])
+                                                (4096, 32, 2, synth.PRIMES_W32),
+                                                (4096, 31, 2, synth.PRIMES_W31)])
 def test_primes_are_largest_ntt_friendly(n, bits, count, table):
     got = oracle.ntt_primes(n, bits, count)
     assert tuple(got) == tuple(table)
@@ -56,6 +57,18 @@ def test_primes_are_largest_ntt_friendly(n, bits, count, table):
     cands = [x for x in range((1 << bits) - 1, table[-1] - 1, -1) if x % (2 * n) == 1]
     primes = [x for x in cands if _trial_prime(x)]
     assert tuple(primes[:count]) == tuple(table)
+
+
+def test_mfma_wide_primes_are_largest_below_digit_reach():
+    # four balanced base-2^8 digits reach 127 * (1 + 2^8 + 2^16 + 2^24); centred
+    # residues (-q/2, q/2] fit when q <= twice that
+    reach = 127 * (1 + 256 + 65536 + 16777216)
+    top = 2 * reach
+    table = synth.PRIMES_W32_MFMA
+    cands = [x for x in range(top, table[-1] - 1, -1) if x % 8192 == 1]
+    primes = [x for x in cands if _trial_prime(x)]
+    assert tuple(primes[:2]) == tuple(table)
+    assert all((q - 1) // 2 <= reach for q in table)
 
 
 def test_q108_primes_product():
