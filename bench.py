@@ -274,43 +274,28 @@ def q108_section(pir):
 
 def w32_section(pir):
     """Two full 32-bit primes (products of residues up to 2^64) on the
-    headline shape (N = 4096, 512 x 512, 8 GiB, VALU layout): 1, 2 and 4
-    clients on the streaming kernel, 32 on the tiled kernel; then the two
-    largest 32-bit primes the INT8 path takes (centred residues) with both
-    layouts: 32 clients on each path.  Median of event-timed calls."""
+    headline shape (N = 4096, 512 x 512, 8 GiB, both layouts): 1, 2 and 4
+    clients on the streaming kernel, 32 on the tiled kernel and on the INT8
+    MFMA path.  Median of event-timed calls."""
     import torch
     import synth
     w = synth.WIDE32
-    db = build_db(pir, w, pir.PIR_LAYOUT_VALU)
-    time.sleep(2.0)
-    res = {"workload": w.name, "primes": list(w.primes), "db_gib": w.db_bytes / 2**30}
-    for B, reps in ((1, 10), (2, 5), (4, 5), (32, 3)):
-        q = make_query(pir, w, B, w.seed)
-        out = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
-        fn = lambda: pir.pir_rowsel(db, q, out, pir.PIR_PATH_VALU)
-        fn()
-        torch.cuda.synchronize()
-        ms = statistics.median(timed_calls(fn, reps))
-        res[f"b{B}_valu"] = {"ms": round(ms, 3), "db_gbs": round(w.db_bytes / (ms * 1e-3) / 1e9, 1),
-                             "mac_per_s": w.slots * 2 * B * w.d0 * w.d1 / (ms * 1e-3)}
-        del q, out
-    pir.pir_db_free(db)
-    w = synth.WIDE32_MFMA
     db = build_db(pir, w, pir.PIR_LAYOUT_VALU | pir.PIR_LAYOUT_MFMA)
     time.sleep(2.0)
-    sub = {"workload": w.name, "primes": list(w.primes)}
-    B = w.clients
-    q = make_query(pir, w, B, w.seed)
-    out = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
-    for name, path in (("mfma", pir.PIR_PATH_MFMA_I8), ("valu", pir.PIR_PATH_VALU)):
+    res = {"workload": w.name, "primes": list(w.primes), "db_gib": w.db_bytes / 2**30}
+    for B, reps, path, name in ((1, 10, pir.PIR_PATH_VALU, "b1_valu"), (2, 5, pir.PIR_PATH_VALU, "b2_valu"),
+                                (4, 5, pir.PIR_PATH_VALU, "b4_valu"), (32, 3, pir.PIR_PATH_VALU, "b32_valu"),
+                                (32, 3, pir.PIR_PATH_MFMA_I8, "b32_mfma_i8")):
+        q = make_query(pir, w, B, w.seed)
+        out = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
         fn = lambda: pir.pir_rowsel(db, q, out, path)
         fn()
         torch.cuda.synchronize()
-        ms = statistics.median(timed_calls(fn, 3))
-        sub[f"b{B}_{name}"] = {"ms": round(ms, 3), "mac_per_s": w.slots * 2 * B * w.d0 * w.d1 / (ms * 1e-3)}
-    del q, out
+        ms = statistics.median(timed_calls(fn, reps))
+        res[name] = {"ms": round(ms, 3), "db_gbs": round(w.db_bytes / (ms * 1e-3) / 1e9, 1),
+                     "mac_per_s": w.slots * 2 * B * w.d0 * w.d1 / (ms * 1e-3)}
+        del q, out
     pir.pir_db_free(db)
-    res["mfma_primes"] = sub
     return res
 
 

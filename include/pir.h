@@ -65,10 +65,9 @@ typedef enum {
  *           60-bit products in one 64-bit sum.  With any prime of 2^30 or
  *           more (products up to 2^64, the 32-bit primes of sec. 2.4.1) the
  *           VALU kernels keep 64-bit sums that count their wraps and the INT8
- *           MFMA path splits centred residues (-q/2, q/2] into four signed
- *           digits, which reach primes up to 4278124286 (twice the largest
- *           digit sum, 127 * (1 + 2^8 + 2^16 + 2^24)); creating a DB with a
- *           larger prime and PIR_LAYOUT_MFMA fails with PIR_EUNSUPPORTED
+ *           MFMA path splits each residue r as r or r - q, whichever lies in
+ *           [-2155905152, 2139062143], the reach of four signed 8-bit digits
+ *           (2^32 - 1 consecutive integers, so every q < 2^32 is served)
  *   d0, d1  DB rows (selector count) and columns, each 1..65536 */
 typedef struct {
     uint32_t n;

@@ -289,10 +289,6 @@ pir_status pir_db_create(const pir_params *params, uint32_t layouts, pir_db **ou
                 db->mod[l] = make_modq(db->p.q[l]);
                 if (db->p.q[l] >= WIDE_Q) db->wide = true;
             }
-            for (uint32_t l = 0; l < db->p.nprimes; ++l)
-                if (db->p.q[l] > MFMA_MAX_Q && (layouts & PIR_LAYOUT_MFMA))
-                    PIR_FAIL(PIR_EUNSUPPORTED, "the MFMA layout needs every prime at most %u, below 2^32 - 2^24 "
-                             "(q[%u] = %u is served by the VALU layout only)", MFMA_MAX_Q, l, db->p.q[l]);
             PIR_HIP(hipGetDevice(&db->device));
             const uint64_t words = db->slots() * db->p.d0 * db->p.d1;
             if (layouts & PIR_LAYOUT_VALU) {

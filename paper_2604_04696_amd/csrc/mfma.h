@@ -16,10 +16,6 @@ struct EpiQ {
 // 2^30 or more: split at 2^16, 64-bit final conversion).
 enum : int { RECOMB_DIRECT = 0, RECOMB_SPLIT = 1, RECOMB_WIDE = 2 };
 
-// Largest prime whose centred residues (-q/2, q/2] four balanced signed
-// 8-bit digits can represent: the digits reach 127 * (1 + 2^8 + 2^16 + 2^24).
-constexpr uint32_t MFMA_MAX_Q = 4278124286u;
-
 // One RowSel instance on the MFMA path.  Its output tiles are numbered
 // [tile0, tile0 + tiles) in the launch's global tile order.
 struct MfmaJob {

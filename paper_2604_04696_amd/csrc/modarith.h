@@ -115,8 +115,8 @@ __device__ __forceinline__ double round_mul(double x, double s) {
 //   MODE = 1:       h = 2^15 h1 + h0 (0 <= h0 < 2^15, |h1| <= 2^15) and
 //                   t = E + h0 c32 + h1 c47, c47 = 2^47 mod q, each product
 //                   below 2^45 in magnitude;
-//   MODE = 2 (any q up to MFMA_MAX_Q; taken when some prime is 2^30 or
-//             more; |h| <= q/2 < 2^31):
+//   MODE = 2 (any q < 2^32; taken when some prime is 2^30 or more;
+//             |h| <= q/2 < 2^31):
 //                   h = 2^16 h1 + h0 (0 <= h0 < 2^16, |h1| <= 2^15) and
 //                   t = E + h0 c32 + h1 c48, c48 = 2^48 mod q, products below
 //                   2^48, |t| < 2^52;
@@ -161,17 +161,33 @@ __host__ __device__ inline bool combine_direct_ok(uint32_t q) {
     return (double)q * c32 <= 3.0 * 2251799813685248.0 - 35184372088832.0;   // 3*2^51 - 2^45
 }
 
-// Balanced signed base-2^8 digits of a 32-bit value read as signed,
-// -2155905152 <= x <= 2139062143: x = sum_i d_i 2^(8i), d_i in [-128, 127]
-// (the top digit of 0 <= x < 2^30 stays within [0, 64]; centred residues of
-// primes up to MFMA_MAX_Q are passed as negative values above q/2).
-// Returned packed as four int8 in one 32-bit word, digit i in byte i.
+// Balanced signed base-2^8 digits: x = sum_i d_i 2^(8i), d_i in [-128, 127],
+// for -2155905152 <= x <= 2139062143 (-0x80808080 .. 0x7F7F7F7F, the whole
+// reach of four such digits).  Returned packed as four int8 in one 32-bit
+// word, digit i in byte i.  The top digit of 0 <= x < 2^30 stays in [0, 64].
 __device__ __forceinline__ uint32_t split_digits(uint32_t x) {
     uint32_t packed = 0;
     int32_t v = (int32_t)x;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         int32_t d = ((v + 128) & 255) - 128;
+        packed |= ((uint32_t)(uint8_t)(int8_t)d) << (8 * i);
+        v = (v - d) >> 8;
+    }
+    return packed;
+}
+
+// The digits of a residue r of any prime q < 2^32.  The reach of four digits
+// holds 2^32 - 1 consecutive integers, so every residue class has a
+// representative in it: x = r for r <= 0x7F7F7F7F, x = r - q above, which is
+// at least 0x7F7F7F80 - q >= -2155905151.  That x may lie below -2^31, so the
+// split runs on 64-bit values.
+__device__ __forceinline__ uint32_t split_digits_window(uint32_t r, uint32_t q) {
+    int64_t v = r > 0x7F7F7F7Fu ? (int64_t)r - (int64_t)q : (int64_t)r;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t d = ((v + 128) & 255) - 128;
         packed |= ((uint32_t)(uint8_t)(int8_t)d) << (8 * i);
         v = (v - d) >> 8;
     }

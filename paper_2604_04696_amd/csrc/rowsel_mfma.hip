@@ -54,8 +54,8 @@ struct ModQ4m {
 // written; 16-byte chunks that straddle [klo, khi) (only when loading a DB
 // in row ranges) are written byte by byte so neighbouring ranges are not
 // overwritten.  CENTER (DBs with a prime of 2^30 or more): a residue above
-// q_l/2 is taken as x - q_l first, so that four balanced digits cover it
-// (point p belongs to prime p / N).
+// 0x7F7F7F7F is taken as x - q_l, so that four balanced digits cover every
+// prime below 2^32 (point p belongs to prime p / N).
 struct DigitCenter {
     uint32_t q[PIR_MAX_PRIMES];
     uint32_t n;
@@ -86,15 +86,19 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
         const bool in = r < r_valid && k >= klo && k < khi && p0 + pp < P;
         v[j] = in ? __builtin_nontemporal_load(src + (uint64_t)r * s_r + (uint64_t)(k - klo) * s_k + p0 + pp)
                   : 0u;
-        if (CENTER && in) {
-            const uint32_t qq = dc.q[(p0 + pp) / dc.n];
-            v[j] = v[j] > qq / 2 ? v[j] - qq : v[j];   // two's complement of the negative residue
-        }
     }
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
         const uint32_t e = tid + 256 * j;
-        tile[e / 4096][(e / 64) % 64][e % 64] = split_digits(v[j]);
+        uint32_t w;
+        if (CENTER) {
+            // the prime of this point (a point past P holds 0, any prime serves)
+            const uint32_t li = (p0 + e % 64) / dc.n;
+            w = split_digits_window(v[j], dc.q[li < PIR_MAX_PRIMES ? li : 0]);
+        } else {
+            w = split_digits(v[j]);
+        }
+        tile[e / 4096][(e / 64) % 64][e % 64] = w;
     }
     __syncthreads();
 

@@ -204,12 +204,15 @@ PRIMES_Q108 = (134176769, 134111233, 134012929, 133963777)
 # Full 32-bit primes (products of residues reach 2^64): the two largest with
 # q = 1 (mod 8192).
 PRIMES_W32 = (4294828033, 4294729729)
-# Wide primes the INT8 path can take once residues are centred to
-# (-q/2, q/2]: the two largest 31-bit ones, and the two largest 32-bit ones not
-# above 4278124286 (= 2 * 2139062143, the reach of four balanced 8-bit
-# digits), all with q = 1 (mod 8192).
+# Further wide primes (parity cases of the 64-bit paths and of the INT8 digit
+# window): the two largest 31-bit ones, and the two largest 32-bit ones not
+# above 4278124286 = 2 * 2139062143 (whose residues would also fit as
+# (-q/2, q/2]), all with q = 1 (mod 8192).
 PRIMES_W31 = (2147377153, 2147352577)
-PRIMES_W32_MFMA = (4278108161, 4277690369)
+PRIMES_W32_SYM = (4278108161, 4277690369)
+# The largest prime below 2^32 with q = 1 (mod 16) (N = 8): its residues come
+# within 527 of the low end of the INT8 digit reach.
+PRIME_W32_TOP_N8 = 4294966769
 
 
 @dataclass(frozen=True)
@@ -259,10 +262,7 @@ BATCHED = Workload("rowsel_n4096_l2_512x512_b64", 3, 4096, PRIMES_N4096, 512, 51
 SERVE_DB = Workload("serve_n4096_l2_1024x1024", 5, 4096, PRIMES_N4096, 1024, 1024, 1,
                     "uniform", note="32 GiB resident DB; requests drawn from a 32-query pool")
 WIDE32 = Workload("rowsel_n4096_l2w32_512x512_b1", 7, 4096, PRIMES_W32, 512, 512, 1, "uniform",
-                  note="two full 32-bit primes (products up to 2^64), 8 GiB DB, VALU layout")
-WIDE32_MFMA = Workload("rowsel_n4096_l2w32m_512x512_b32", 8, 4096, PRIMES_W32_MFMA, 512, 512, 32, "uniform",
-                       note="the two largest 32-bit primes the INT8 path takes (centred residues), "
-                            "8 GiB DB, both layouts, a batch of 32")
+                  note="two full 32-bit primes (products up to 2^64), 8 GiB DB")
 PAPER_Q108 = Workload("rowsel_n4096_l4q108_256x512_b32", 6, 4096, PRIMES_Q108, 256, 512, 32,
                       "uniform", note="four 27-bit limbs (Q ~ 2^108) and D0 = 256 as in the paper's "
                       "setting; 8 GiB DB; one client and a batch of 32")

@@ -1,8 +1,8 @@
 """GPU parity with primes of 2^30 or more (products of residues reach 2^64):
 the VALU path keeps 64-bit sums that count their wraps, the NTTs keep 64-bit
-intermediates, and the INT8 MFMA path takes centred residues and the wide
-recombination for primes up to 4278124286 (refusing larger ones).  Against
-the CPU oracle word for word (tolerance 0)."""
+intermediates, and the INT8 MFMA path splits each residue r as r or r - q,
+whichever four signed 8-bit digits reach, and recombines in its wide form.
+Against the CPU oracle word for word (tolerance 0)."""
 import numpy as np
 import pytest
 
@@ -111,23 +111,20 @@ def test_wide_coeff_query_matches_oracle(pir, n):
     assert np.array_equal(np_u32(out).reshape(want.shape), want)
 
 
-def test_wide_refuses_mfma(pir):
-    with pytest.raises(pir.PirError, match="below 2"):
-        pir.pir_db_create(pir.make_params(64, W32, 8, 8))
-
-
 # ------------------------------------------------ INT8 MFMA path, centred digits
-W31, W32M = synth.PRIMES_W31, synth.PRIMES_W32_MFMA
+W31, W32S = synth.PRIMES_W31, synth.PRIMES_W32_SYM
 
 MFMA_SHAPES = [
     # (N, primes, D0, D1, B): 64 x 128 tiles (2B <= 64) and 128 x 64 tiles
-    (64, W32M, 37, 40, 3),
+    (64, W32, 37, 40, 3),
     (64, W31, 130, 33, 17),
-    (32, W32M, 100, 24, 40),
+    (32, W32S, 100, 24, 40),
+    (8, (synth.PRIME_W32_TOP_N8,), 30, 20, 4),
     # a wide prime beside a 30-bit one (one launch, the wide recombination)
-    (16, (W32M[0], 1073692673), 70, 20, 9),
+    (16, (W32[0], 1073692673), 70, 20, 9),
     # D0 above the 2048-row int32 accumulation chunk
-    (16, W32M, 2100, 6, 2),
+    (16, W32, 2100, 6, 2),
+    (16, W32S, 2100, 6, 2),
 ]
 
 
@@ -150,16 +147,22 @@ def test_wide_mfma_matches_oracle(pir, shape):
         assert np.array_equal(got, want), f"path {path}: {(got != want).sum()} of {want.size} words differ"
 
 
-def test_wide_mfma_extreme_centred_residues(pir):
-    # DB residues (q-1)/2 and queries (q+1)/2 (centred: +(q-1)/2 and -(q-1)/2,
-    # the largest magnitudes four digits must carry), D0 above one K chunk
-    n, primes, d0, d1, B = 16, W32M, 4100, 5, 2
-    say("wide mfma extremes")
+EDGE = [(16, W32), (16, W32S), (8, (synth.PRIME_W32_TOP_N8,))]
+
+
+@pytest.mark.parametrize("n,primes", EDGE, ids=[f"q{p[0]}" for _, p in EDGE])
+def test_wide_mfma_digit_window_edges(pir, n, primes):
+    # residues at both ends of the digit window: T = 0x7F7F7F7F is split as
+    # +T (all digits 127) and T + 1 as T + 1 - q (near -0x80808080); DB rows
+    # alternate T + 1 and T, component 0 of every query is T + 1 and
+    # component 1 is T, so products of every sign pairing reach about 2^62;
+    # D0 spans three int32 accumulation chunks
+    d0, d1, B, T = 4100, 5, 2, 0x7F7F7F7F
+    say("wide mfma window edges", primes)
     dhat = np.empty((d0, d1, len(primes), n), dtype=np.uint32)
     qv = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
-    for l, q in enumerate(primes):
-        dhat[..., l, :] = (q - 1) // 2
-        qv[..., l, :] = (q + 1) // 2
+    dhat[0::2], dhat[1::2] = T + 1, T
+    qv[:, 0], qv[:, 1] = T + 1, T
     want = oracle.rowsel(qv, dhat, primes)
     db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_MFMA)
     pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
@@ -169,10 +172,29 @@ def test_wide_mfma_extreme_centred_residues(pir):
     assert np.array_equal(np_u32(out).reshape(want.shape), want)
 
 
+@pytest.mark.parametrize("B", [2, 5])
+def test_wide_mfma_all_q_minus_one(pir, B):
+    # every residue q - 1 (split as -1): every output is D0 mod q
+    n, primes, d0, d1 = 16, W32, 4100, 6
+    say("wide mfma q-1, B", B)
+    dhat = np.empty((d0, d1, len(primes), n), dtype=np.uint32)
+    qv = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
+    for l, q in enumerate(primes):
+        dhat[..., l, :] = q - 1
+        qv[..., l, :] = q - 1
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_MFMA)
+    pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+    out = empty_u32(B * 2 * d1 * len(primes) * n)
+    pir.pir_rowsel(db, to_dev(qv), out, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    want = np.array([d0 % q for q in primes], dtype=np.uint32)
+    assert np.all(np_u32(out).reshape(B, 2, d1, len(primes), n) == want[:, None])
+
+
 def test_wide_mfma_grouped_with_narrow_instance(pir):
     # one grouped launch over a wide and a 30-bit instance: the widest
     # recombination serves both
-    specs = [(64, W31, 40, 24, 5), (64, synth.PRIMES_N4096, 70, 16, 20)]
+    specs = [(64, W32, 40, 24, 5), (64, synth.PRIMES_N4096, 70, 16, 20), (64, W31, 33, 9, 2)]
     items, wants = [], []
     for i, (n, primes, d0, d1, B) in enumerate(specs):
         coeffs = synth.db_coeffs(87 + i, d0, d1, len(primes), n)

@@ -48,7 +48,8 @@ def _trial_prime(n):
                                                 (4096, 30, 2, synth.PRIMES_N4096),
                                                 (4096, 27, 4, synth.PRIMES_Q108),
                                                 (4096, 32, 2, synth.PRIMES_W32),
-                                                (4096, 31, 2, synth.PRIMES_W31)])
+                                                (4096, 31, 2, synth.PRIMES_W31),
+                                                (8, 32, 1, (synth.PRIME_W32_TOP_N8,))])
 def test_primes_are_largest_ntt_friendly(n, bits, count, table):
     got = oracle.ntt_primes(n, bits, count)
     assert tuple(got) == tuple(table)
@@ -59,12 +60,12 @@ def test_primes_are_largest_ntt_friendly(n, bits, count, table):
     assert tuple(primes[:count]) == tuple(table)
 
 
-def test_mfma_wide_primes_are_largest_below_digit_reach():
-    # four balanced base-2^8 digits reach 127 * (1 + 2^8 + 2^16 + 2^24); centred
-    # residues (-q/2, q/2] fit when q <= twice that
+def test_w32_sym_primes_are_largest_below_twice_digit_reach():
+    # four balanced base-2^8 digits reach 127 * (1 + 2^8 + 2^16 + 2^24); the
+    # table holds the two largest NTT-friendly primes at most twice that
     reach = 127 * (1 + 256 + 65536 + 16777216)
     top = 2 * reach
-    table = synth.PRIMES_W32_MFMA
+    table = synth.PRIMES_W32_SYM
     cands = [x for x in range(top, table[-1] - 1, -1) if x % 8192 == 1]
     primes = [x for x in cands if _trial_prime(x)]
     assert tuple(primes[:2]) == tuple(table)
