@@ -13,6 +13,10 @@ Functions and the passage each follows:
   * ``negacyclic_mul``              -- schoolbook product mod (X^N + 1, q).
   * ``rowsel``                      -- the point-wise GEMM of sec. 2.2 / 2.3:
        out[b][c][n][l][j] = sum_k Q[b][c][k][l][j] * DB[k][n][l][j]  mod q_l.
+  * ``coltor`` (module)             -- the first ColTor stage: RNS
+       reconstruction, digit decomposition and the external product
+       (sec. 2.2, 2.4.2), in Python integers.
+  * ``rlwe`` (module)               -- toy RLWE encryption and decryption.
 """
 from __future__ import annotations
 
