@@ -154,6 +154,33 @@ pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
 pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff_dev, uint32_t B,
                             uint32_t *out_dev, pir_path path, void *hip_stream);
 
+/* First ColTor stage (sec. 2.2, ColTor; the external product of sec. 2.4.2):
+ * for each of B clients and each pair of ciphertexts (columns 2t, 2t+1)
+ *   out[b][t] = ct[b][2t] + RGSW_b [x] (ct[b][2t+1] - ct[b][2t])
+ * with [x] the external product: both polynomials of the difference are
+ * taken to the coefficient domain, every coefficient is rebuilt mod
+ * Q = prod q_l (RNS reconstruction), centred into (-Q/2, Q/2] and cut into
+ * `ell` digits of base z = 2^log2z (digits 0..ell-2 in [-z/2, z/2), the
+ * last one the rest: within [-z/2, z/2 + 1] since z^ell > Q), and the
+ * 2*ell digit polynomials, back in the NTT domain, multiply-accumulate
+ * against the RGSW rows.  A bit-b RGSW thus keeps column 2t (b = 0) or takes
+ * column 2t+1 (b = 1).  An unpaired last column (odd ncols) passes through.
+ * ring:    n and the primes (d0, d1 are ignored); the same rules as
+ *          pir_db_create, and L*N <= 16384 (the paper's N = 4096 with four
+ *          limbs is the largest), else PIR_EUNSUPPORTED
+ * ct_dev:  [B][2][ncols][L][N] NTT-domain residues < q_l (the layout of
+ *          pir_rowsel's output)
+ * rgsw_dev: [B][2][ell][2][L][N]: row (p, i) is the ciphertext pair that
+ *          multiplies digit i of input polynomial p, NTT domain
+ * out_dev: [B][2][(ncols+1)/2][L][N]; must overlap neither input.
+ * 1 <= ell <= 8, 1 <= log2z <= 30, z^ell > Q and 2^(log2z-1) + 1 below every
+ * prime, else PIR_EINVAL.  B = 0 is a no-op; ncols >= 1 otherwise.
+ * Stream-ordered scratch holds the digits (B * ceil(ncols/2) * 2 * ell * N
+ * int32).  Asynchronous on hip_stream like pir_rowsel. */
+pir_status pir_coltor_stage(const pir_params *ring, const uint32_t *ct_dev, uint32_t B, uint32_t ncols,
+                            const uint32_t *rgsw_dev, uint32_t log2z, uint32_t ell, uint32_t *out_dev,
+                            void *hip_stream);
+
 /* One RowSel instance of a grouped call. */
 typedef struct {
     const pir_db *db;

@@ -58,6 +58,7 @@ SIGNATURES = {
     "pir_rowsel": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
     "pir_rowsel_coeff": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
     "pir_rowsel_grouped": (_i32, [_vp, _u32, _i32, _vp]),
+    "pir_coltor_stage": (_i32, [ctypes.POINTER(pir_params), _vp, _u32, _u32, _vp, _u32, _u32, _vp, _vp]),
     "pir_rowsel_grouped_tile": (_i32, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "pir_clock": (ctypes.c_double, []),
     "pir_server_create": (_i32, [_vp, _vp, ctypes.POINTER(_vp)]),
@@ -219,6 +220,17 @@ def pir_rowsel_coeff(db: Db, query_coeff, out, path: int = PIR_PATH_AUTO, stream
     """RowSel on a coefficient-domain query (transformed to the NTT domain by the library)."""
     qp, B, op = _rowsel_args(db, query_coeff, out, B)
     _check(lib().pir_rowsel_coeff(db.handle, qp, B, op, path, _stream(stream)), "pir_rowsel_coeff")
+
+
+def pir_coltor_stage(n: int, primes, ct, B: int, ncols: int, rgsw, log2z: int, ell: int, out, stream=None):
+    """First ColTor stage: ct [B][2][ncols][L][N], rgsw [B][2][ell][2][L][N]
+    -> out [B][2][(ncols+1)//2][L][N] (device tensors of 32-bit words)."""
+    ring = make_params(n, primes, 1, 1)
+    cp = _ptr(ct, "ct") if B else 0
+    rp = _ptr(rgsw, "rgsw") if B else 0
+    op = _ptr(out, "out") if B else 0
+    _check(lib().pir_coltor_stage(ctypes.byref(ring), cp, B, ncols, rp, log2z, ell, op, _stream(stream)),
+           "pir_coltor_stage")
 
 
 class pir_rowsel_item(ctypes.Structure):

@@ -392,6 +392,26 @@ pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff, uint32_t 
     });
 }
 
+pir_status pir_coltor_stage(const pir_params *ring, const uint32_t *ct, uint32_t B, uint32_t ncols,
+                            const uint32_t *rgsw, uint32_t log2z, uint32_t ell, uint32_t *out, void *stream) {
+    return guarded([&] {
+        PIR_REQUIRE(ring != nullptr, "ring is NULL");
+        pir_params r = *ring;
+        r.d0 = r.d1 = 1;
+        validate_params(r);
+        coltor_check_gadget(r, log2z, ell);
+        if (B == 0) return;
+        PIR_REQUIRE(ncols >= 1, "ncols must be at least 1");
+        PIR_REQUIRE(ct && rgsw && out, "ct, rgsw and out must not be NULL");
+        const size_t LN = (size_t)r.n * r.nprimes * 4;
+        const size_t nct = (size_t)B * 2 * ncols * LN, nrg = (size_t)B * 4 * ell * LN,
+                     nout = (size_t)B * 2 * ((ncols + 1) / 2) * LN;
+        PIR_REQUIRE(!overlaps(out, nout, ct, nct), "out overlaps ct");
+        PIR_REQUIRE(!overlaps(out, nout, rgsw, nrg), "out overlaps rgsw");
+        launch_coltor_stage(r, ct, B, ncols, rgsw, log2z, ell, out, as_stream(stream));
+    });
+}
+
 pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count, pir_path path, void *stream) {
     return guarded([&] {
         PIR_REQUIRE(count == 0 || items != nullptr, "items is NULL");

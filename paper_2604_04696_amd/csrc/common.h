@@ -83,8 +83,8 @@ struct ModQ {
 };
 
 // Primes at or above this bound take the wide forms (64-bit intermediates,
-// no lazy sums) on the VALU path and in the NTTs; the MFMA path needs primes
-// below it.
+// no lazy sums) on the VALU path and in the NTTs, and on the MFMA path the
+// digit window and the wide recombination.
 constexpr uint32_t WIDE_Q = 1u << 30;
 
 ModQ make_modq(uint32_t q);
@@ -228,6 +228,11 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
 // Query front end: coefficient-domain query -> NTT-domain query, both in the
 // boundary layout [B][2][D0][L][N].
 void launch_query_ntt(const pir_db &db, const uint32_t *q_coeff, uint32_t B, uint32_t *q_ntt, hipStream_t st);
+
+// First ColTor stage (coltor.hip).
+void coltor_check_gadget(const pir_params &ring, uint32_t log2z, uint32_t ell);
+void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B, uint32_t ncols,
+                         const uint32_t *rgsw, uint32_t log2z, uint32_t ell, uint32_t *out, hipStream_t st);
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st);
 void release_group_plans();

@@ -9,6 +9,7 @@ import subprocess
 import pytest
 
 import paper_2604_04696_amd as pir
+import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", h) for h in ("pir.h", "pir_synth.h")]
@@ -148,3 +149,22 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pir, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         pir.lib()
+
+
+@pytest.mark.parametrize("n,primes,log2z,ell,status,frag", [
+    (4096, synth.PRIMES_Q108, 22, 4, "PIR_EINVAL", "must exceed Q"),
+    (4096, synth.PRIMES_Q108, 30, 4, "PIR_EINVAL", "below every prime"),
+    (4096, synth.PRIMES_Q108, 22, 9, "PIR_EINVAL", "ell must be"),
+    (4096, synth.PRIMES_Q108, 0, 5, "PIR_EINVAL", "log2z must be"),
+    (16384, (1073643521, 1073479681), 22, 3, "PIR_EUNSUPPORTED", "at most 16384"),
+    (4096, synth.PRIMES_Q108, 22, 5, "PIR_EINVAL", "must not be NULL"),
+])
+def test_coltor_stage_validation(n, primes, log2z, ell, status, frag):
+    # all checks run on the host before any device work
+    ring = pir.make_params(n, primes, 1, 1)
+    st = pir.lib().pir_coltor_stage(ctypes.byref(ring), None, 1, 2, None, log2z, ell, None, None)
+    assert st == getattr(pir, status), pir.pir_last_error()
+    assert frag in pir.pir_last_error()
+    # B = 0 is a no-op once the parameters are valid
+    if status == "PIR_EINVAL" and frag == "must not be NULL":
+        assert pir.lib().pir_coltor_stage(ctypes.byref(ring), None, 0, 2, None, log2z, ell, None, None) == pir.PIR_OK
