@@ -299,6 +299,37 @@ def w32_section(pir):
     return res
 
 
+def coltor_section(pir, reps=5):
+    """First ColTor stage at the paper's setting: 32 clients, the 512 RowSel
+    output ciphertexts of each (N = 4096, four 27-bit limbs), gadget z = 2^22,
+    ell = 5; random NTT-domain ciphertexts and RGSW rows.  Median of
+    event-timed calls."""
+    import torch
+    import synth
+    n, primes, log2z, ell, B, ncols = 4096, synth.PRIMES_Q108, 22, 5, 32, 512
+    L = len(primes)
+    ct = torch.empty(B * 2 * ncols * L * n, dtype=torch.int32, device="cuda")
+    pir.pir_synth_query(ct, synth.stream_key(9, synth.TAG_QUERY), 0, B, ncols, primes, n)
+    rg = torch.empty(B * 2 * ell * 2 * L * n, dtype=torch.int32, device="cuda")
+    pir.pir_synth_query(rg, synth.stream_key(9, synth.TAG_QUERY, 1), 0, B * ell * 2, 1, primes, n)
+    out = torch.empty(B * 2 * (ncols // 2) * L * n, dtype=torch.int32, device="cuda")
+    fn = lambda: pir.pir_coltor_stage(n, primes, ct, B, ncols, rg, log2z, ell, out)
+    fn()
+    torch.cuda.synchronize()
+    time.sleep(1.0)
+    ms = statistics.median(timed_calls(fn, reps))
+    nodes = B * ncols // 2
+    io = (ct.numel() + rg.numel() + out.numel()) * 4
+    # transforms per node: 2 polynomials x L limbs inverse, 2 x ell x L forward
+    ntts = nodes * (2 * L + 2 * ell * L)
+    res = {"workload": f"coltor_stage1_n{n}_l4q108_z{log2z}l{ell}_b{B}_{ncols}cols", "ms": round(ms, 3),
+           "nodes": nodes, "nodes_per_s": nodes / (ms * 1e-3), "io_gib": round(io / 2**30, 3),
+           "io_gbs": round(io / (ms * 1e-3) / 1e9, 1), "ntt_per_s": ntts / (ms * 1e-3),
+           "butterflies_per_s": ntts * (n // 2) * (n.bit_length() - 1) / (ms * 1e-3)}
+    del ct, rg, out
+    return res
+
+
 def make_query_sub(pir, w, sub):
     import torch
     import synth
@@ -340,6 +371,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-client figures")
     ap.add_argument("--no-grouped", action="store_true", help="skip the grouped-instances figures")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving figures")
+    ap.add_argument("--no-coltor", action="store_true", help="skip the ColTor-stage figures")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--serve-loads", default="0.7,0.9",
                     help="offered loads as fractions of the saturated rate")
@@ -479,6 +511,11 @@ def main():
         line["w32"] = w32_section(pir)
         torch.cuda.empty_cache()
         log(f"32-bit primes: {line['w32']}")
+
+    if not args.no_coltor:
+        line["coltor"] = coltor_section(pir)
+        torch.cuda.empty_cache()
+        log(f"ColTor stage: {line['coltor']}")
 
     if not args.no_grouped:
         log("grouped instances")

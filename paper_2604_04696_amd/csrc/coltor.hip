@@ -30,6 +30,7 @@
 
 #include "common.h"
 #include "modarith.h"
+#include "nttreg.h"
 
 namespace pir {
 
@@ -45,6 +46,7 @@ struct ColtorPrimes {
     uint32_t ninv[PIR_MAX_PRIMES], ninv_s[PIR_MAX_PRIMES];
     uint32_t crt_c[PIR_MAX_PRIMES], crt_cs[PIR_MAX_PRIMES];   // (Q/q_l)^-1 mod q_l and its companion
     uint64_t mu[PIR_MAX_PRIMES];                               // Barrett constants of reduce64
+    ModQ mod[PIR_MAX_PRIMES];
     uint32_t qhat[PIR_MAX_PRIMES][4];                          // Q/q_l, 32-bit limbs, low first
     uint32_t Q[4], Qhalf[4];                                   // Q and floor(Q/2)
 };
@@ -122,8 +124,8 @@ coltor_dcp_kernel(const uint32_t *__restrict__ ct, uint32_t ncols, uint32_t nout
 }
 
 // ------------------------------------------------- kernel 2: NTT + products
-// grid: nodes * L blocks.  Thread tid owns points j = tid + k * CT_THREADS.
-constexpr int CT_MAXK = 16384 / CT_THREADS;   // points per thread at n = 16384
+// One-stage-per-barrier form for small rings (N < 256).  grid: nodes * L
+// blocks; thread tid owns points j = tid + k * CT_THREADS.
 
 template <int K>
 __global__ void __launch_bounds__(CT_THREADS)
@@ -196,6 +198,104 @@ coltor_mac_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ 
     }
 }
 
+// ------------------------------- kernel 2, register-blocked (N >= 256)
+// The RGSW rows are first permuted so that word 16t + r of a row holds point
+// bitrev(16t + r) (rgsw_permute_kernel): after the register-blocked forward
+// transform thread t holds exactly those points of a digit polynomial in
+// registers 0..15, so each multiply reads 64 contiguous bytes per thread and
+// no digit polynomial goes back through LDS to natural order.  Products are
+// summed lazily in 64 bits (at most 16 below 2^60 each for q < 2^30;
+// wrap-counting sums for wider primes) and reduced once; the two results
+// then take one LDS exchange each to natural order, where ct0 is added.
+__global__ void __launch_bounds__(256)
+rgsw_permute_kernel(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, uint64_t total,
+                    uint32_t logn) {
+    const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const uint32_t n = 1u << logn, j = (uint32_t)(e & (n - 1));
+    out[e] = in[(e - j) + (__brev(j) >> (32 - logn))];
+}
+
+template <int LOGN, bool WIDE>
+__global__ void __launch_bounds__((1u << LOGN) / QR)
+coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ rgsw_p,
+                      const int32_t *__restrict__ digits, uint32_t *__restrict__ out, uint32_t ncols,
+                      uint32_t nout, uint32_t L, uint32_t ell, ColtorPrimes pr) {
+    constexpr uint32_t n = 1u << LOGN, T = n / QR;
+    extern __shared__ uint32_t s[];                  // n + n/16 words
+    const uint32_t t = threadIdx.x;
+    const uint32_t l = blockIdx.x % L, node = blockIdx.x / L;
+    const uint32_t b = node / nout, tn = node % nout;
+    const uint32_t q = pr.q[l];
+    const uint64_t LN = (uint64_t)L * n;
+    const uint32_t *c0 = ct + ((uint64_t)(b * 2) * ncols + 2 * tn) * LN + (uint64_t)l * n;   // component 0
+    uint32_t *o = out + ((uint64_t)(b * 2) * nout + tn) * LN + (uint64_t)l * n;
+    const uint64_t c_in = (uint64_t)ncols * LN, c_out = (uint64_t)nout * LN;   // component strides
+
+    if (2 * tn + 1 >= ncols) {                       // unpaired column passes through
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < QR; ++r) o[c * c_out + t + r * T] = c0[c * c_in + t + r * T];
+        return;
+    }
+    const ModQ &m = pr.mod[l];
+    const uint32_t *tw = pr.fwd[l], *tws = tw + n;
+    uint64_t acc[2][QR];
+    uint32_t wraps[2][QR];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < QR; ++r) acc[c][r] = 0, wraps[c][r] = 0;
+
+    for (uint32_t p = 0; p < 2; ++p) {
+        for (uint32_t i = 0; i < ell; ++i) {
+            const int32_t *dg = digits + (((uint64_t)node * 2 + p) * ell + i) * n;
+            uint32_t v[QR];
+#pragma unroll
+            for (int r = 0; r < QR; ++r) {
+                const int32_t d = dg[qf_elem(t, r, LOGN - 4)];
+                v[r] = d < 0 ? (uint32_t)(d + (int64_t)q) : (uint32_t)d;
+            }
+            ntt_reg_block<LOGN, WIDE>(v, t, s, tw, tws, q);
+            const uint4 *row = reinterpret_cast<const uint4 *>(
+                rgsw_p + ((((uint64_t)b * 2 + p) * ell + i) * 2) * LN + (uint64_t)l * n + (uint64_t)t * QR);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const uint4 w4 = row[c * (LN / 4) + g];
+                    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int r = 4 * g + k;
+                        const uint32_t x = WIDE ? v[r] : qf_reduce4(v[r], q, 2 * q);
+                        if (WIDE) mad_wide(acc[c][r], wraps[c][r], x, w[k]);
+                        else acc[c][r] += (uint64_t)x * w[k];
+                    }
+                }
+            }
+        }
+    }
+    // register r of thread t holds point bitrev(16t + r): one exchange per
+    // output polynomial to natural order, then out = ct0 + sum
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QR; ++r) {
+            const uint32_t res = WIDE ? reduce_wide(acc[c][r], wraps[c][r], m) : reduce64(acc[c][r], m);
+            s[qf_pad(__brev(t * QR + r) >> (32 - LOGN))] = res;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QR; ++r) {
+            const uint32_t j = t + r * T;
+            o[c * c_out + j] = add_mod_w(c0[c * c_in + j], s[qf_pad(j)], q);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host
 static void split128(u128 x, uint32_t (&w)[4]) {
     for (int i = 0; i < 4; ++i) w[i] = (uint32_t)(x >> (32 * i));
@@ -227,6 +327,7 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
     uint32_t logn = 0;
     while ((1u << logn) < n) ++logn;
     ColtorPrimes pr{};
+    bool wide = false;
     u128 Q = 1;
     for (uint32_t l = 0; l < L; ++l) Q *= ring.q[l];
     split128(Q, pr.Q);
@@ -244,7 +345,9 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
         const uint32_t c = pow_mod((uint64_t)(qh % q), q - 2, q);
         pr.crt_c[l] = c;
         pr.crt_cs[l] = shoup32(c, q);
-        pr.mu[l] = make_modq(q).mu;
+        pr.mod[l] = make_modq(q);
+        pr.mu[l] = pr.mod[l].mu;
+        wide = wide || q >= WIDE_Q;
     }
     const uint64_t nodes = (uint64_t)B * nout;
     if (nodes == 0) return;
@@ -258,18 +361,45 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
     coltor_dcp_kernel<<<(uint32_t)(nodes * 2), CT_THREADS, lds1, st>>>(ct, ncols, nout, L, n, logn, log2z, ell,
                                                                        dg, pr);
     PIR_LAUNCH_CHECK();
+    if (n >= 256) {
+        // RGSW rows in the transform's register order, then the blocked kernel
+        const uint64_t rg_words = (uint64_t)B * 4 * ell * L * n;
+        PIR_REQUIRE(rg_words / 256 < (1ull << 31), "ColTor launch too large");
+        StreamScratch rgp(rg_words * sizeof(uint32_t), st);
+        rgsw_permute_kernel<<<(uint32_t)((rg_words + 255) / 256), 256, 0, st>>>(rgsw, rgp.as<uint32_t>(),
+                                                                             rg_words, logn);
+        PIR_LAUNCH_CHECK();
+        const size_t lds = (size_t)(n + n / 16) * sizeof(uint32_t);
+        auto go2 = [&](auto kern) {
+            PIR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            kern<<<(uint32_t)(nodes * L), n / QR, lds, st>>>(ct, rgp.as<uint32_t>(), dg, out, ncols, nout, L, ell,
+                                                               pr);
+        };
+        auto pick = [&](auto w) {
+            constexpr bool W = decltype(w)::value;
+            switch (logn) {
+                case 8: go2(&coltor_mac_reg_kernel<8, W>); break;
+                case 9: go2(&coltor_mac_reg_kernel<9, W>); break;
+                case 10: go2(&coltor_mac_reg_kernel<10, W>); break;
+                case 11: go2(&coltor_mac_reg_kernel<11, W>); break;
+                case 12: go2(&coltor_mac_reg_kernel<12, W>); break;
+                case 13: go2(&coltor_mac_reg_kernel<13, W>); break;
+                default: go2(&coltor_mac_reg_kernel<14, W>); break;
+            }
+        };
+        if (wide) pick(std::true_type{});
+        else pick(std::false_type{});
+        PIR_LAUNCH_CHECK();
+        return;
+    }
     const size_t lds2 = (size_t)n * sizeof(uint32_t);
     auto go = [&](auto kern) {
         PIR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
         kern<<<(uint32_t)(nodes * L), CT_THREADS, lds2, st>>>(ct, rgsw, dg, out, ncols, nout, L, n, logn, ell, pr);
     };
-    const uint32_t K = (n + CT_THREADS - 1) / CT_THREADS;
-    if (K <= 1) go(&coltor_mac_kernel<1>);
-    else if (K <= 2) go(&coltor_mac_kernel<2>);
-    else if (K <= 4) go(&coltor_mac_kernel<4>);
-    else if (K <= 8) go(&coltor_mac_kernel<8>);
-    else go(&coltor_mac_kernel<CT_MAXK>);
+    go(&coltor_mac_kernel<1>);   // n < 256: one point per thread
     PIR_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,96 @@
+// Register-blocked negacyclic NTT helpers shared by the query front end and
+// the ColTor stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "modarith.h"
+
+namespace pir {
+
+// Register-blocked transform for N >= 256: a polynomial is handled by
+// T = N/16 threads that each keep 16 of its values in registers.  The
+// butterfly stages (bit x of the pair distance, from logN-1 down to 0) run in
+// chunks of up to four: during a chunk the register index r of a thread
+// covers four index bits [lo, lo+4) (for the last chunk, bits [0, 4)), so
+// every pair of the chunk's stages is local to one thread; between chunks
+// the values are redistributed through LDS (padded one word per 16).  The
+// element index of (thread t, register r) with register bits starting at lo:
+//   e = (t mod 2^lo) | r << lo | (t >> lo) << (lo + 4).
+// The butterfly of stage x on pair (e, e + 2^x) uses the psi power of group
+// e >> (x+1) among N >> (x+1) groups, exactly as the one-stage-per-barrier
+// form; values stay in [0, 4q) between stages (lazy butterflies) and are
+// reduced once before the store.  A last exchange writes point bitrev(e) so that global stores are in
+// natural point order and coalesced.
+constexpr int QR = 16;   // values per thread
+
+__device__ __forceinline__ uint32_t qf_pad(uint32_t e) { return e + (e >> 4); }
+
+// Lazy butterfly (Harvey): inputs and outputs in [0, 4q), which fits 32 bits
+// for q < 2^30.  x is first brought into [0, 2q) (x - 2q wraps above x when
+// x < 2q, so the minimum picks the reduced value); Shoup's product without
+// its final correction lies in [0, 2q) for any 32-bit y.
+__device__ __forceinline__ void qf_bfly(uint32_t &x, uint32_t &y, uint32_t w, uint32_t ws, uint32_t q,
+                                        uint32_t q2) {
+    const uint32_t xr = min(x, x - q2);
+    const uint32_t t = y * w - __umulhi(y, ws) * q;
+    x = xr + t;
+    y = xr - t + q2;
+}
+
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ uint32_t qf_reduce4(uint32_t x, uint32_t q, uint32_t q2) {
+    x = min(x, x - q2);
+    return min(x, x - q);
+}
+__device__ __forceinline__ uint32_t qf_elem(uint32_t t, uint32_t r, uint32_t lo) {
+    return (t & ((1u << lo) - 1)) | (r << lo) | ((t >> lo) << (lo + 4));
+}
+
+// Forward transform of one polynomial held by all N/16 threads of a block
+// (N = 2^LOGN >= 256).  On entry register r of thread t holds element
+// qf_elem(t, r, LOGN - 4) of the natural coefficient order; on return it
+// holds element 16t + r of the transform, which is point bitrev(16t + r).
+// WIDE (q >= 2^30): canonical butterflies with 64-bit intermediates, outputs
+// in [0, q); otherwise lazy butterflies, outputs in [0, 4q).  poly is LDS of
+// N + N/16 words; the first exchange begins with a barrier, so earlier reads
+// of poly by the block are complete before it is overwritten.
+template <int LOGN, bool WIDE>
+__device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uint32_t *poly,
+                                              const uint32_t *tw, const uint32_t *tws, uint32_t q) {
+    constexpr uint32_t n = 1u << LOGN;
+    uint32_t lo = LOGN - 4;
+#pragma unroll
+    for (int hi = LOGN; hi > 0; hi -= 4) {
+        const int clo = hi - 4 > 0 ? hi - 4 : 0;
+        const uint32_t rlo = (uint32_t)clo;
+        if (rlo != lo) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, r, lo))] = v[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(qf_elem(t, r, rlo))];
+            lo = rlo;
+        }
+#pragma unroll
+        for (int x = hi - 1; x >= clo; --x) {
+            const uint32_t bit = 1u << (x - (int)lo), mgroups = n >> (x + 1);
+#pragma unroll
+            for (int r = 0; r < QR; ++r) {
+                if (r & bit) continue;
+                const uint32_t gi = mgroups + (qf_elem(t, r, lo) >> (x + 1));
+                if (WIDE) {
+                    const uint32_t u = v[r], w = mul_shoup_w(v[r | bit], tw[gi], tws[gi], q);
+                    v[r] = add_mod_w(u, w, q);
+                    v[r | bit] = sub_mod(u, w, q);
+                } else {
+                    qf_bfly(v[r], v[r | bit], tw[gi], tws[gi], q, 2 * q);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace pir

@@ -30,6 +30,7 @@
 #include "common.h"
 #include "mfma.h"
 #include "modarith.h"
+#include "nttreg.h"
 
 namespace pir {
 
@@ -94,44 +95,8 @@ query_ntt_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, uint
     }
 }
 
-// Register-blocked transform for N >= 256: a polynomial is handled by
-// T = N/16 threads that each keep 16 of its values in registers.  The
-// butterfly stages (bit x of the pair distance, from logN-1 down to 0) run in
-// chunks of up to four: during a chunk the register index r of a thread
-// covers four index bits [lo, lo+4) (for the last chunk, bits [0, 4)), so
-// every pair of the chunk's stages is local to one thread; between chunks
-// the values are redistributed through LDS (padded one word per 16).  The
-// element index of (thread t, register r) with register bits starting at lo:
-//   e = (t mod 2^lo) | r << lo | (t >> lo) << (lo + 4).
-// The butterfly of stage x on pair (e, e + 2^x) uses the psi power of group
-// e >> (x+1) among N >> (x+1) groups, exactly as the one-stage-per-barrier
-// form; values stay in [0, 4q) between stages (lazy butterflies) and are
-// reduced once before the store.  A last exchange writes point bitrev(e) so that global stores are in
-// natural point order and coalesced.
-constexpr int QR = 16;   // values per thread
-
-__device__ __forceinline__ uint32_t qf_pad(uint32_t e) { return e + (e >> 4); }
-
-// Lazy butterfly (Harvey): inputs and outputs in [0, 4q), which fits 32 bits
-// for q < 2^30.  x is first brought into [0, 2q) (x - 2q wraps above x when
-// x < 2q, so the minimum picks the reduced value); Shoup's product without
-// its final correction lies in [0, 2q) for any 32-bit y.
-__device__ __forceinline__ void qf_bfly(uint32_t &x, uint32_t &y, uint32_t w, uint32_t ws, uint32_t q,
-                                        uint32_t q2) {
-    const uint32_t xr = min(x, x - q2);
-    const uint32_t t = y * w - __umulhi(y, ws) * q;
-    x = xr + t;
-    y = xr - t + q2;
-}
-
-// [0, 4q) -> [0, q)
-__device__ __forceinline__ uint32_t qf_reduce4(uint32_t x, uint32_t q, uint32_t q2) {
-    x = min(x, x - q2);
-    return min(x, x - q);
-}
-__device__ __forceinline__ uint32_t qf_elem(uint32_t t, uint32_t r, uint32_t lo) {
-    return (t & ((1u << lo) - 1)) | (r << lo) | ((t >> lo) << (lo + 4));
-}
+// Register-blocked transform for N >= 256 (the scheme and helpers are in
+// nttreg.h).
 
 template <int LOGN, bool WIDE>
 __global__ void __launch_bounds__(QF_THREADS)
