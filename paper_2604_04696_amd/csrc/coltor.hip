@@ -45,6 +45,7 @@ struct ColtorPrimes {
     uint32_t q[PIR_MAX_PRIMES];
     uint32_t ninv[PIR_MAX_PRIMES], ninv_s[PIR_MAX_PRIMES];
     uint32_t crt_c[PIR_MAX_PRIMES], crt_cs[PIR_MAX_PRIMES];   // (Q/q_l)^-1 mod q_l and its companion
+    uint32_t crt_cn[PIR_MAX_PRIMES], crt_cns[PIR_MAX_PRIMES]; // the same times N^-1 (folds the INTT scale)
     uint64_t mu[PIR_MAX_PRIMES];                               // Barrett constants of reduce64
     ModQ mod[PIR_MAX_PRIMES];
     uint32_t qhat[PIR_MAX_PRIMES][4];                          // Q/q_l, 32-bit limbs, low first
@@ -120,6 +121,74 @@ coltor_dcp_kernel(const uint32_t *__restrict__ ct, uint32_t ncols, uint32_t nout
             v = (v - d) >> log2z;
         }
         dst[(uint64_t)(ell - 1) * n + j] = (int32_t)v;
+    }
+}
+
+// ------------------------------- kernel 1, register-blocked (N >= 256)
+// L*N/16 threads: thread group l (N/16 threads) transforms limb l with 16
+// values per thread, then all limbs of a coefficient meet in LDS for the
+// reconstruction.  Shared by the decomposition: (Q/q_l)^-1 N^-1 mod q_l.
+__device__ __forceinline__ void dcp_coefficient(const uint32_t *x, uint32_t L, uint32_t j, uint32_t log2z,
+                                                uint32_t ell, uint64_t n, int32_t *dst, const ColtorPrimes &pr,
+                                                bool wide) {
+    const u128 Q = u128_of(pr.Q), Qhalf = u128_of(pr.Qhalf);
+    u128 acc = 0;
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t q = pr.q[l];
+        const uint32_t y = wide ? mul_shoup_w(x[l], pr.crt_cn[l], pr.crt_cns[l], q)
+                                : mul_shoup(x[l], pr.crt_cn[l], pr.crt_cns[l], q);
+        const u128 term = (u128)y * u128_of(pr.qhat[l]);
+        u128 sum = acc + term;
+        if (sum < acc || sum >= Q) sum -= Q;
+        acc = sum;
+    }
+    const i128 zhalf = (i128)1 << (log2z - 1);
+    const i128 zmask = ((i128)1 << log2z) - 1;
+    i128 v = acc > Qhalf ? -(i128)(Q - acc) : (i128)acc;
+    for (uint32_t i = 0; i + 1 < ell; ++i) {
+        const i128 d = ((v + zhalf) & zmask) - zhalf;
+        dst[i * n + j] = (int32_t)d;
+        v = (v - d) >> log2z;
+    }
+    dst[(ell - 1) * n + j] = (int32_t)v;
+}
+
+template <int LOGN, bool WIDE>
+__global__ void __launch_bounds__(1024)
+coltor_dcp_reg_kernel(const uint32_t *__restrict__ ct, uint32_t ncols, uint32_t nout, uint32_t L,
+                      uint32_t log2z, uint32_t ell, int32_t *__restrict__ digits, ColtorPrimes pr) {
+    constexpr uint32_t n = 1u << LOGN, T = n / QR, PW = n + n / 16;
+    extern __shared__ uint32_t s[];                  // [L][PW]
+    const uint32_t tid = threadIdx.x, l = tid / T, t = tid % T;
+    const uint32_t p = blockIdx.x % 2, node = blockIdx.x / 2;
+    const uint32_t b = node / nout, tn = node % nout;
+    if (2 * tn + 1 >= ncols) return;                 // unpaired column: no product
+    const uint64_t LN = (uint64_t)L * n;
+    const uint32_t *c0 = ct + ((uint64_t)(b * 2 + p) * ncols + 2 * tn) * LN + (uint64_t)l * n;
+    const uint32_t *c1 = c0 + LN;
+    const uint32_t q = pr.q[l];
+    uint32_t *poly = s + l * PW;
+
+    // difference; point j goes to position bitrev(j)
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+        const uint32_t j = t + r * T;
+        poly[qf_pad(__brev(j) >> (32 - LOGN))] = sub_mod(c1[j], c0[j], q);
+    }
+    __syncthreads();
+    uint32_t v[QR];
+#pragma unroll
+    for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(t * QR + r)];
+    intt_reg_block<LOGN, WIDE>(v, t, poly, pr.inv[l], pr.inv[l] + n, q);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, r, LOGN - 4))] = v[r];
+    __syncthreads();
+    int32_t *dst = digits + ((uint64_t)node * 2 + p) * ell * n;
+    for (uint32_t j = tid; j < n; j += L * T) {
+        uint32_t x[PIR_MAX_PRIMES];
+        for (uint32_t k = 0; k < L; ++k) x[k] = s[k * PW + qf_pad(j)];
+        dcp_coefficient(x, L, j, log2z, ell, n, dst, pr, WIDE);
     }
 }
 
@@ -224,7 +293,10 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
     constexpr uint32_t n = 1u << LOGN, T = n / QR;
     extern __shared__ uint32_t s[];                  // n + n/16 words
     const uint32_t t = threadIdx.x;
-    const uint32_t l = blockIdx.x % L, node = blockIdx.x / L;
+    // the L limb blocks of a node, and consecutive nodes of a client, run on
+    // one XCD: the node's digits and the client's RGSW rows stay in its L2
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t l = lb % L, node = lb / L;
     const uint32_t b = node / nout, tn = node % nout;
     const uint32_t q = pr.q[l];
     const uint64_t LN = (uint64_t)L * n;
@@ -345,6 +417,8 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
         const uint32_t c = pow_mod((uint64_t)(qh % q), q - 2, q);
         pr.crt_c[l] = c;
         pr.crt_cs[l] = shoup32(c, q);
+        pr.crt_cn[l] = (uint32_t)((uint64_t)c * t.n_inv % q);
+        pr.crt_cns[l] = shoup32(pr.crt_cn[l], q);
         pr.mod[l] = make_modq(q);
         pr.mu[l] = pr.mod[l].mu;
         wide = wide || q >= WIDE_Q;
@@ -355,11 +429,34 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
     StreamScratch scratch((size_t)nodes * 2 * ell * n * sizeof(int32_t), st);
     int32_t *dg = scratch.as<int32_t>();
 
-    const size_t lds1 = (size_t)L * n * sizeof(uint32_t);
-    PIR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&coltor_dcp_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1));
-    coltor_dcp_kernel<<<(uint32_t)(nodes * 2), CT_THREADS, lds1, st>>>(ct, ncols, nout, L, n, logn, log2z, ell,
-                                                                       dg, pr);
+    if (n >= 256) {
+        const size_t lds = (size_t)L * (n + n / 16) * sizeof(uint32_t);
+        auto go1 = [&](auto kern) {
+            PIR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            kern<<<(uint32_t)(nodes * 2), L * (n / QR), lds, st>>>(ct, ncols, nout, L, log2z, ell, dg, pr);
+        };
+        auto pick1 = [&](auto w) {
+            constexpr bool W = decltype(w)::value;
+            switch (logn) {
+                case 8: go1(&coltor_dcp_reg_kernel<8, W>); break;
+                case 9: go1(&coltor_dcp_reg_kernel<9, W>); break;
+                case 10: go1(&coltor_dcp_reg_kernel<10, W>); break;
+                case 11: go1(&coltor_dcp_reg_kernel<11, W>); break;
+                case 12: go1(&coltor_dcp_reg_kernel<12, W>); break;
+                case 13: go1(&coltor_dcp_reg_kernel<13, W>); break;
+                default: go1(&coltor_dcp_reg_kernel<14, W>); break;
+            }
+        };
+        if (wide) pick1(std::true_type{});
+        else pick1(std::false_type{});
+    } else {
+        const size_t lds1 = (size_t)L * n * sizeof(uint32_t);
+        PIR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&coltor_dcp_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1));
+        coltor_dcp_kernel<<<(uint32_t)(nodes * 2), CT_THREADS, lds1, st>>>(ct, ncols, nout, L, n, logn, log2z,
+                                                                           ell, dg, pr);
+    }
     PIR_LAUNCH_CHECK();
     if (n >= 256) {
         // RGSW rows in the transform's register order, then the blocked kernel

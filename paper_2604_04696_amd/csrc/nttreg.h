@@ -93,4 +93,60 @@ __device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uin
     }
 }
 
+// Lazy Gentleman-Sande butterfly: (x, y) -> (x + y, (x - y) w), inputs and
+// outputs in [0, 2q) for q < 2^30 (x - y + 2q < 4q fits 32 bits; Shoup's
+// product without its correction lies in [0, 2q)).
+__device__ __forceinline__ void qf_gs_bfly(uint32_t &x, uint32_t &y, uint32_t w, uint32_t ws, uint32_t q,
+                                           uint32_t q2) {
+    const uint32_t sum = x + y, d = x - y + q2;
+    x = min(sum, sum - q2);
+    y = d * w - __umulhi(d, ws) * q;
+}
+
+// Inverse transform (without the 1/N scale) of one polynomial held by N/16
+// threads, stages ascending in chunks of four bits.  On entry register r of
+// thread t holds position 16t + r of the bit-reversed arrangement (point
+// bitrev(16t + r)); on return it holds N times coefficient
+// qf_elem(t, r, LOGN - 4).  tw are the inverse twiddles (psi^-1 powers at
+// bit-reversed indices) with companions at tws.  WIDE (q >= 2^30):
+// canonical butterflies, outputs in [0, q); otherwise lazy, [0, 2q) from
+// inputs in [0, 2q).  poly: LDS of N + N/16 words owned by these threads;
+// exchanges begin with a block-wide barrier.
+template <int LOGN, bool WIDE>
+__device__ __forceinline__ void intt_reg_block(uint32_t (&v)[QR], uint32_t t, uint32_t *poly,
+                                               const uint32_t *tw, const uint32_t *tws, uint32_t q) {
+    constexpr uint32_t n = 1u << LOGN;
+    uint32_t lo = 0;
+#pragma unroll
+    for (int clo = 0; clo < LOGN; clo += 4) {
+        const int chi = clo + 4 < LOGN ? clo + 4 : LOGN;
+        const uint32_t rlo = (uint32_t)(clo < LOGN - 4 ? clo : LOGN - 4);   // registers cover [rlo, rlo + 4)
+        if (rlo != lo) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, r, lo))] = v[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(qf_elem(t, r, rlo))];
+            lo = rlo;
+        }
+#pragma unroll
+        for (int x = clo; x < chi; ++x) {
+            const uint32_t bit = 1u << (x - (int)lo), mgroups = n >> (x + 1);
+#pragma unroll
+            for (int r = 0; r < QR; ++r) {
+                if (r & bit) continue;
+                const uint32_t gi = mgroups + (qf_elem(t, r, lo) >> (x + 1));
+                if (WIDE) {
+                    const uint32_t u = v[r], w = v[r | bit];
+                    v[r] = add_mod_w(u, w, q);
+                    v[r | bit] = mul_shoup_w(sub_mod(u, w, q), tw[gi], tws[gi], q);
+                } else {
+                    qf_gs_bfly(v[r], v[r | bit], tw[gi], tws[gi], q, 2 * q);
+                }
+            }
+        }
+    }
+}
+
 }  // namespace pir
