@@ -134,3 +134,40 @@ def test_coltor_errors(pir):
         pir.pir_coltor_stage(16384, (1073643521, 1073479681), ct, 1, 2, rg, 22, 3, out)
     pir.pir_coltor_stage(n, primes, ct, 0, 2, rg, 22, 5, out)   # no-op
     torch.cuda.synchronize()
+
+
+def test_coltor_two_stages_match_oracle(pir):
+    # a tournament is one call per stage on the previous stage's output
+    n, primes, log2z, ell, B, ncols = 64, Q108, 22, 5, 2, 7
+    say("coltor two stages")
+    cts = residues(305, (B, 2, ncols), primes, n)
+    rg1 = residues(306, (B, 2, ell, 2), primes, n)
+    rg2 = residues(307, (B, 2, ell, 2), primes, n)
+    want = coltor.coltor_stage(coltor.coltor_stage(cts, rg1, primes, log2z, ell), rg2, primes, log2z, ell)
+    mid = empty_u32(B * 2 * 4 * len(primes) * n)
+    out = empty_u32(want.size)
+    pir.pir_coltor_stage(n, primes, to_dev(cts), B, ncols, to_dev(rg1), log2z, ell, mid)
+    pir.pir_coltor_stage(n, primes, mid, B, 4, to_dev(rg2), log2z, ell, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_u32(out).reshape(want.shape), want)
+
+
+def test_coltor_full_tournament_selects_column(pir):
+    # log2(ncols) stages with noiseless RGSW of the bits of j* (least significant
+    # first) leave exactly column j* of each client
+    n, primes, log2z, ell, B, ncols = 4096, Q108, 22, 5, 3, 64
+    L = len(primes)
+    say("coltor tournament")
+    cts = residues(308, (B, 2, ncols), primes, n)
+    jstar = [0, 37, 63]
+    cur, cols = to_dev(cts), ncols
+    stage = 0
+    while cols > 1:
+        rg = np.stack([coltor.trivial_rgsw((jstar[b] >> stage) & 1, primes, n, log2z, ell) for b in range(B)])
+        nxt = empty_u32(B * 2 * ((cols + 1) // 2) * L * n)
+        pir.pir_coltor_stage(n, primes, cur, B, cols, to_dev(rg), log2z, ell, nxt)
+        cur, cols, stage = nxt, (cols + 1) // 2, stage + 1
+    torch.cuda.synchronize()
+    got = np_u32(cur).reshape(B, 2, L, n)
+    for b in range(B):
+        assert np.array_equal(got[b], cts[b, :, jstar[b]]), b
