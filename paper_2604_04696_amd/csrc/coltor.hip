@@ -50,6 +50,11 @@ struct ColtorPrimes {
     ModQ mod[PIR_MAX_PRIMES];
     uint32_t qhat[PIR_MAX_PRIMES][4];                          // Q/q_l, 32-bit limbs, low first
     uint32_t Q[4], Qhalf[4];                                   // Q and floor(Q/2)
+    // the short form (Q < 2^125 and log2z * ell <= 126): C = sum_{i < ell-1} (z/2) z^i
+    // and C - Q mod 2^128, and 1/q_l in binary64
+    uint32_t C[4], CmQ[4];
+    double qinv[PIR_MAX_PRIMES];
+    uint32_t fast;
 };
 
 __device__ __forceinline__ u128 u128_of(const uint32_t (&w)[4]) {
@@ -128,9 +133,52 @@ coltor_dcp_kernel(const uint32_t *__restrict__ ct, uint32_t ncols, uint32_t nout
 // L*N/16 threads: thread group l (N/16 threads) transforms limb l with 16
 // values per thread, then all limbs of a coefficient meet in LDS for the
 // reconstruction.  Shared by the decomposition: (Q/q_l)^-1 N^-1 mod q_l.
+// The short form: y_l = x_l (Q/q_l)^-1 N^-1 mod q_l; S = sum_l y_l Q/q_l taken
+// mod 2^128 and k = floor(sum_l y_l / q_l) in binary64 (S - k Q is the
+// reconstruction up to one Q either way: the estimate's error is far below 1,
+// and S - k Q lies in (-Q, 2Q), inside the signed 128-bit range for
+// Q < 2^125).  The balanced digits of the centred value v are the plain
+// base-z digits of v + C, each less z/2 (C = sum_{i < ell-1} (z/2) z^i: adding
+// z/2 to each digit position is what the balanced recursion's rounding does),
+// and the last one is what remains after ell-1 arithmetic shifts; the value
+// stays below 2^126 since log2z * ell <= 126.  Digit i is then one mask of the
+// low word and a 4-word funnel shift.
+__device__ __forceinline__ void dcp_coefficient_short(const uint32_t *x, uint32_t L, uint32_t j, uint32_t log2z,
+                                                      uint32_t ell, uint64_t n, int32_t *dst,
+                                                      const ColtorPrimes &pr, bool wide) {
+    const u128 Q = u128_of(pr.Q);
+    u128 S = 0;
+    double fk = 0.0;
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t q = pr.q[l];
+        const uint32_t y = wide ? mul_shoup_w(x[l], pr.crt_cn[l], pr.crt_cns[l], q)
+                                : mul_shoup(x[l], pr.crt_cn[l], pr.crt_cns[l], q);
+        fk = fma((double)y, pr.qinv[l], fk);
+        S += (u128)y * u128_of(pr.qhat[l]);
+    }
+    u128 v = S - (u128)(uint32_t)fk * Q;
+    if ((i128)v < 0) v += Q;
+    else if (v >= Q) v -= Q;
+    v += v > u128_of(pr.Qhalf) ? u128_of(pr.CmQ) : u128_of(pr.C);
+    uint32_t w0 = (uint32_t)v, w1 = (uint32_t)(v >> 32), w2 = (uint32_t)(v >> 64), w3 = (uint32_t)(v >> 96);
+    const uint32_t zmask = (1u << log2z) - 1, zhalf = 1u << (log2z - 1);
+    for (uint32_t i = 0; i + 1 < ell; ++i) {
+        dst[i * n + j] = (int32_t)(w0 & zmask) - (int32_t)zhalf;
+        w0 = __builtin_amdgcn_alignbit(w1, w0, log2z);
+        w1 = __builtin_amdgcn_alignbit(w2, w1, log2z);
+        w2 = __builtin_amdgcn_alignbit(w3, w2, log2z);
+        w3 = (uint32_t)((int32_t)w3 >> log2z);
+    }
+    dst[(ell - 1) * n + j] = (int32_t)w0;
+}
+
 __device__ __forceinline__ void dcp_coefficient(const uint32_t *x, uint32_t L, uint32_t j, uint32_t log2z,
                                                 uint32_t ell, uint64_t n, int32_t *dst, const ColtorPrimes &pr,
                                                 bool wide) {
+    if (pr.fast) {
+        dcp_coefficient_short(x, L, j, log2z, ell, n, dst, pr, wide);
+        return;
+    }
     const u128 Q = u128_of(pr.Q), Qhalf = u128_of(pr.Qhalf);
     u128 acc = 0;
     for (uint32_t l = 0; l < L; ++l) {
@@ -404,6 +452,13 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
     for (uint32_t l = 0; l < L; ++l) Q *= ring.q[l];
     split128(Q, pr.Q);
     split128(Q >> 1, pr.Qhalf);
+    pr.fast = (Q >> 125) == 0 && log2z * ell <= 126;
+    if (pr.fast) {
+        u128 C = 0, zi = 1;
+        for (uint32_t i = 0; i + 1 < ell; ++i, zi <<= log2z) C += zi << (log2z - 1);
+        split128(C, pr.C);
+        split128(C - Q, pr.CmQ);
+    }
     for (uint32_t l = 0; l < L; ++l) {
         const uint32_t q = ring.q[l];
         const NttTables &t = ntt_tables(q, n);
@@ -420,6 +475,7 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
         pr.crt_cn[l] = (uint32_t)((uint64_t)c * t.n_inv % q);
         pr.crt_cns[l] = shoup32(pr.crt_cn[l], q);
         pr.mod[l] = make_modq(q);
+        pr.qinv[l] = 1.0 / (double)q;
         pr.mu[l] = pr.mod[l].mu;
         wide = wide || q >= WIDE_Q;
     }
