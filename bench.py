@@ -326,7 +326,22 @@ def coltor_section(pir, reps=5):
            "nodes": nodes, "nodes_per_s": nodes / (ms * 1e-3), "io_gib": round(io / 2**30, 3),
            "io_gbs": round(io / (ms * 1e-3) / 1e9, 1), "ntt_per_s": ntts / (ms * 1e-3),
            "butterflies_per_s": ntts * (n // 2) * (n.bit_length() - 1) / (ms * 1e-3)}
-    del ct, rg, out
+    # the whole tournament: log2(512) = 9 stages down to one ciphertext per
+    # client (the same RGSW rows serve every stage here; the arithmetic is that
+    # of distinct ones)
+    bufs = [torch.empty(B * 2 * (ncols >> s) * L * n, dtype=torch.int32, device="cuda") for s in range(1, 10)]
+
+    def tournament():
+        cur, cols = ct, ncols
+        for buf in bufs:
+            pir.pir_coltor_stage(n, primes, cur, B, cols, rg, log2z, ell, buf)
+            cur, cols = buf, cols // 2
+
+    tournament()
+    torch.cuda.synchronize()
+    res["tournament_ms"] = round(statistics.median(timed_calls(tournament, 3)), 3)
+    res["tournament_stages"] = len(bufs)
+    del ct, rg, out, bufs
     return res
 
 
