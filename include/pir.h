@@ -176,7 +176,9 @@ pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff_dev, uint3
  * 1 <= ell <= 8, 1 <= log2z <= 30, z^ell > Q and 2^(log2z-1) + 1 below every
  * prime, else PIR_EINVAL.  B = 0 is a no-op; ncols >= 1 otherwise.
  * Stream-ordered scratch holds the digits (B * ceil(ncols/2) * 2 * ell * N
- * int32).  Asynchronous on hip_stream like pir_rowsel. */
+ * int32) and, for N >= 256, the RGSW rows permuted to the transforms'
+ * register order (the size of rgsw_dev).  Asynchronous on hip_stream like
+ * pir_rowsel; a tournament is one call per stage on the previous output. */
 pir_status pir_coltor_stage(const pir_params *ring, const uint32_t *ct_dev, uint32_t B, uint32_t ncols,
                             const uint32_t *rgsw_dev, uint32_t log2z, uint32_t ell, uint32_t *out_dev,
                             void *hip_stream);
