@@ -333,7 +333,7 @@ rgsw_permute_kernel(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
     out[e] = in[(e - j) + (__brev(j) >> (32 - logn))];
 }
 
-template <int LOGN, bool WIDE>
+template <int LOGN, int MODE>
 __global__ void __launch_bounds__((1u << LOGN) / QR)
 coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ rgsw_p,
                       const int32_t *__restrict__ digits, uint32_t *__restrict__ out, uint32_t ncols,
@@ -377,7 +377,7 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
                 const int32_t d = dg[qf_elem(t, r, LOGN - 4)];
                 v[r] = d < 0 ? (uint32_t)(d + (int64_t)q) : (uint32_t)d;
             }
-            ntt_reg_block<LOGN, WIDE>(v, t, s, tw, tws, q);
+            ntt_reg_block<LOGN, MODE>(v, t, s, tw, tws, q);
             const uint4 *row = reinterpret_cast<const uint4 *>(
                 rgsw_p + ((((uint64_t)b * 2 + p) * ell + i) * 2) * LN + (uint64_t)l * n + (uint64_t)t * QR);
 #pragma unroll
@@ -389,8 +389,11 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int r = 4 * g + k;
-                        const uint32_t x = WIDE ? v[r] : qf_reduce4(v[r], q, 2 * q);
-                        if (WIDE) mad_wide(acc[c][r], wraps[c][r], x, w[k]);
+                        // NTT_GROW: the unreduced value (below (1 + 2 logN) q)
+                        // goes into the 64-bit sum; the host checks 2 ell of
+                        // these products fit
+                        const uint32_t x = MODE == NTT_LAZY ? qf_reduce4(v[r], q, 2 * q) : v[r];
+                        if (MODE == NTT_WIDE) mad_wide(acc[c][r], wraps[c][r], x, w[k]);
                         else acc[c][r] += (uint64_t)x * w[k];
                     }
                 }
@@ -404,7 +407,7 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
-            const uint32_t res = WIDE ? reduce_wide(acc[c][r], wraps[c][r], m) : reduce64(acc[c][r], m);
+            const uint32_t res = MODE == NTT_WIDE ? reduce_wide(acc[c][r], wraps[c][r], m) : reduce64(acc[c][r], m);
             s[qf_pad(__brev(t * QR + r) >> (32 - LOGN))] = res;
         }
         __syncthreads();
@@ -529,20 +532,28 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
             kern<<<(uint32_t)(nodes * L), n / QR, lds, st>>>(ct, rgp.as<uint32_t>(), dg, out, ncols, nout, L, ell,
                                                                pr);
         };
-        auto pick = [&](auto w) {
-            constexpr bool W = decltype(w)::value;
+        // unreduced butterflies when every prime leaves room for logN stages of
+        // growth and 2 ell products of the grown values fit a 64-bit sum
+        bool grow = !wide;
+        for (uint32_t l = 0; l < L && grow; ++l) {
+            const u128 bound = (u128)(1 + 2 * logn) * ring.q[l];
+            grow = bound < ((u128)1 << 32) && bound * ring.q[l] * (2 * ell) < ((u128)1 << 64);
+        }
+        auto pick = [&](auto mode) {
+            constexpr int M = decltype(mode)::value;
             switch (logn) {
-                case 8: go2(&coltor_mac_reg_kernel<8, W>); break;
-                case 9: go2(&coltor_mac_reg_kernel<9, W>); break;
-                case 10: go2(&coltor_mac_reg_kernel<10, W>); break;
-                case 11: go2(&coltor_mac_reg_kernel<11, W>); break;
-                case 12: go2(&coltor_mac_reg_kernel<12, W>); break;
-                case 13: go2(&coltor_mac_reg_kernel<13, W>); break;
-                default: go2(&coltor_mac_reg_kernel<14, W>); break;
+                case 8: go2(&coltor_mac_reg_kernel<8, M>); break;
+                case 9: go2(&coltor_mac_reg_kernel<9, M>); break;
+                case 10: go2(&coltor_mac_reg_kernel<10, M>); break;
+                case 11: go2(&coltor_mac_reg_kernel<11, M>); break;
+                case 12: go2(&coltor_mac_reg_kernel<12, M>); break;
+                case 13: go2(&coltor_mac_reg_kernel<13, M>); break;
+                default: go2(&coltor_mac_reg_kernel<14, M>); break;
             }
         };
-        if (wide) pick(std::true_type{});
-        else pick(std::false_type{});
+        if (wide) pick(std::integral_constant<int, NTT_WIDE>{});
+        else if (grow) pick(std::integral_constant<int, NTT_GROW>{});
+        else pick(std::integral_constant<int, NTT_LAZY>{});
         PIR_LAUNCH_CHECK();
         return;
     }

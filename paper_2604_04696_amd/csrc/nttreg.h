@@ -48,15 +48,24 @@ __device__ __forceinline__ uint32_t qf_elem(uint32_t t, uint32_t r, uint32_t lo)
     return (t & ((1u << lo) - 1)) | (r << lo) | ((t >> lo) << (lo + 4));
 }
 
+// Butterfly forms of ntt_reg_block.
+enum : int {
+    NTT_LAZY = 0,   // q < 2^30: Harvey's butterfly, values in [0, 4q)
+    NTT_WIDE = 1,   // q >= 2^30: canonical, 64-bit intermediates, values in [0, q)
+    NTT_GROW = 2,   // (1 + 2 logN) q < 2^32: no correction at all, (x + t, x - t + 2q)
+};
+
 // Forward transform of one polynomial held by all N/16 threads of a block
 // (N = 2^LOGN >= 256).  On entry register r of thread t holds element
-// qf_elem(t, r, LOGN - 4) of the natural coefficient order; on return it
-// holds element 16t + r of the transform, which is point bitrev(16t + r).
-// WIDE (q >= 2^30): canonical butterflies with 64-bit intermediates, outputs
-// in [0, q); otherwise lazy butterflies, outputs in [0, 4q).  poly is LDS of
-// N + N/16 words; the first exchange begins with a barrier, so earlier reads
-// of poly by the block are complete before it is overwritten.
-template <int LOGN, bool WIDE>
+// qf_elem(t, r, LOGN - 4) of the natural coefficient order (a residue below
+// q); on return it holds element 16t + r of the transform, which is point
+// bitrev(16t + r), congruent mod q and bounded by the form: NTT_WIDE [0, q),
+// NTT_LAZY [0, 4q), NTT_GROW [0, (1 + 2 logN) q) (each stage adds at most 2q,
+// since Shoup's product without its correction lies in [0, 2q) for any
+// 32-bit input).  poly is LDS of N + N/16 words; the first exchange begins
+// with a barrier, so earlier reads of poly by the block are complete before
+// it is overwritten.
+template <int LOGN, int MODE>
 __device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uint32_t *poly,
                                               const uint32_t *tw, const uint32_t *tws, uint32_t q) {
     constexpr uint32_t n = 1u << LOGN;
@@ -81,10 +90,15 @@ __device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uin
             for (int r = 0; r < QR; ++r) {
                 if (r & bit) continue;
                 const uint32_t gi = mgroups + (qf_elem(t, r, lo) >> (x + 1));
-                if (WIDE) {
+                if (MODE == NTT_WIDE) {
                     const uint32_t u = v[r], w = mul_shoup_w(v[r | bit], tw[gi], tws[gi], q);
                     v[r] = add_mod_w(u, w, q);
                     v[r | bit] = sub_mod(u, w, q);
+                } else if (MODE == NTT_GROW) {
+                    const uint32_t y = v[r | bit];
+                    const uint32_t tt = y * tw[gi] - __umulhi(y, tws[gi]) * q;
+                    v[r | bit] = v[r] + 2 * q - tt;
+                    v[r] = v[r] + tt;
                 } else {
                     qf_bfly(v[r], v[r | bit], tw[gi], tws[gi], q, 2 * q);
                 }
