@@ -171,3 +171,34 @@ def test_coltor_full_tournament_selects_column(pir):
     got = np_u32(cur).reshape(B, 2, L, n)
     for b in range(B):
         assert np.array_equal(got[b], cts[b, :, jstar[b]]), b
+
+
+@pytest.mark.parametrize("log2z,ell", [(22, 5), (26, 5)], ids=["short_form", "exact_form"])
+def test_coltor_decomposition_boundaries(pir, log2z, ell):
+    # ct1 - ct0 whose coefficients sit on the decomposition's boundaries:
+    # 0, 1, Q-1 (= -1), floor(Q/2) (the largest kept positive), floor(Q/2)+1
+    # (the first taken negative), +-z/2 and neighbours, then random values;
+    # z^ell = 2^110 takes the short reconstruction, 2^130 the exact one
+    import oracle as orc
+    n, primes, B, ncols = 256, Q108, 2, 2
+    L = len(primes)
+    Q = coltor.modulus(primes)
+    z = 1 << log2z
+    special = [0, 1, Q - 1, Q // 2, Q // 2 + 1, z // 2, z // 2 - 1, z // 2 + 1, Q - z // 2, Q - z // 2 - 1,
+               z, Q - z, (z // 2) * (1 + z), Q - (z // 2) * (1 + z)]
+    rng = np.random.default_rng(11)
+    vals = special + [int.from_bytes(rng.bytes(14), "little") % Q for _ in range(n - len(special))]
+    say("coltor boundaries", log2z, ell)
+    cts = residues(309, (B, 2, ncols), primes, n)
+    for b in range(B):
+        for p in range(2):
+            for l, q in enumerate(primes):
+                coef = np.array([v % int(q) for v in vals[p * 3:] + vals[:p * 3]], dtype=np.uint32)
+                d = orc.ntt_forward(coef, int(q))
+                cts[b, p, 1, l] = ((cts[b, p, 0, l].astype(np.int64) + d) % int(q)).astype(np.uint32)
+    rg = residues(310, (B, 2, ell, 2), primes, n)
+    want = coltor.coltor_stage(cts, rg, primes, log2z, ell)
+    out = empty_u32(want.size)
+    pir.pir_coltor_stage(n, primes, to_dev(cts), B, ncols, to_dev(rg), log2z, ell, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_u32(out).reshape(want.shape), want)
