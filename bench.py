@@ -284,7 +284,8 @@ def w32_section(pir):
     time.sleep(2.0)
     res = {"workload": w.name, "primes": list(w.primes), "db_gib": w.db_bytes / 2**30}
     for B, reps, path, name in ((1, 10, pir.PIR_PATH_VALU, "b1_valu"), (2, 5, pir.PIR_PATH_VALU, "b2_valu"),
-                                (4, 5, pir.PIR_PATH_VALU, "b4_valu"), (32, 3, pir.PIR_PATH_VALU, "b32_valu"),
+                                (4, 5, pir.PIR_PATH_VALU, "b4_valu"), (2, 5, pir.PIR_PATH_MFMA_I8, "b2_mfma_i8"),
+                                (4, 5, pir.PIR_PATH_MFMA_I8, "b4_mfma_i8"), (32, 3, pir.PIR_PATH_VALU, "b32_valu"),
                                 (32, 3, pir.PIR_PATH_MFMA_I8, "b32_mfma_i8")):
         q = make_query(pir, w, B, w.seed)
         out = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")

@@ -187,8 +187,11 @@ static pir_path resolve_path(const pir_db &db, uint32_t B, pir_path path) {
     const bool has_v = db.layouts & PIR_LAYOUT_VALU, has_m = db.layouts & PIR_LAYOUT_MFMA;
     if (path == PIR_PATH_AUTO) {
         // one or two clients are HBM bound: the streaming VALU kernel reads the
-        // DB once at full bandwidth; beyond that the matrix cores win
-        if (has_v && (!has_m || B <= 2)) return PIR_PATH_VALU;
+        // DB once at full bandwidth; beyond that the matrix cores win.  With a
+        // prime of 2^30 or more every client is its own streaming pass (two
+        // 64-bit words per sum), so the matrix cores win from two clients on
+        // (8 GiB DB, two 32-bit primes: 1.9 ms on MFMA against 2.8 ms)
+        if (has_v && (!has_m || B <= (db.wide ? 1u : 2u))) return PIR_PATH_VALU;
         return PIR_PATH_MFMA_I8;
     }
     PIR_REQUIRE(path == PIR_PATH_VALU || path == PIR_PATH_MFMA_I8, "unknown path %d", (int)path);
