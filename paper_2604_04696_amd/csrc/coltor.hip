@@ -12,20 +12,25 @@
 // multiply-accumulate against the RGSW rows into two polynomials.  An
 // unpaired last column (odd count) passes through.
 //
-// Two kernels:
-//   coltor_dcp_kernel  one block per (node, input polynomial): the
+// Two kernels, each in a register-blocked form for N >= 256 (16 values per
+// thread, up to four butterfly stages per LDS exchange) and a
+// one-stage-per-barrier form for smaller rings:
+//   decomposition      one block per (node, input polynomial): the
 //                      difference of the two columns and its inverse NTT for
-//                      all L limbs in LDS (L*N <= 16384 words), then the
+//                      all L limbs (L*N <= 16384 words in LDS), then the
 //                      reconstruction and decomposition, coefficient by
 //                      coefficient; digits go out as int32 [node][2][ell][N]
 //                      (ell*N words per polynomial instead of L*N residues
 //                      per digit: each limb reduces them on load);
-//   coltor_mac_kernel  one block per (node, limb): for each of the 2*ell
+//   multiply-accumulate one block per (node, limb): for each of the 2*ell
 //                      digit polynomials, the residues mod q_l, the forward
-//                      NTT in LDS and the product with the two RGSW
-//                      components of that row, accumulated in registers;
-//                      then ct0 is added and both output polynomials stored.
-// Every modular step uses the forms that hold for any prime below 2^32.
+//                      NTT and the product with the two RGSW components of
+//                      that row, summed in registers; then ct0 is added and
+//                      both output polynomials stored.
+// The butterfly and sum forms are chosen per launch from the primes: wide
+// (64-bit intermediates) for any prime of 2^30 or more, lazy below, and
+// unreduced forward butterflies when (1 + 2 logN) q < 2^32; the small-ring
+// forms use the wide arithmetic throughout.
 #include <type_traits>
 
 #include "common.h"
