@@ -208,3 +208,32 @@ def test_wide_mfma_grouped_with_narrow_instance(pir):
     torch.cuda.synchronize()
     for (db, q, B, out), want in zip(items, wants):
         assert np.array_equal(np_u32(out).reshape(want.shape), want)
+
+
+def test_wide_serving_matches_oracle(pir):
+    # the continuous-batching server on a DB of two full 32-bit primes: its
+    # MFMA steps take the digit window and the wide recombination
+    import time
+    n, primes, d0, d1 = 64, W32, 40, 30
+    say("wide serving")
+    coeffs = synth.db_coeffs(93, d0, d1, len(primes), n)
+    dhat = oracle.ntt_db(coeffs, primes)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_MFMA)
+    pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+    queries = synth.query_uniform(94, 6, d0, primes, n)
+    wants = oracle.rowsel(queries, dhat, primes)
+    srv = pir.pir_server_create(db, max_clients=4, chunks=3)
+    outs = [empty_u32(2 * d1 * len(primes) * n) for _ in range(6)]
+    qs = [to_dev(queries[i]) for i in range(6)]
+    schedule = {0: [(i, qs[i], outs[i]) for i in range(4)], 2: [(i, qs[i], outs[i]) for i in range(4, 6)]}
+    got, turn, t0 = {}, 0, time.time()
+    while len(got) < 6:
+        for c in pir.pir_serve_step(srv, schedule.get(turn, ())):
+            got[c.id] = c
+        turn += 1
+        assert time.time() - t0 < 60, f"only {len(got)} of 6 completions"
+    torch.cuda.synchronize()
+    for i in range(6):
+        assert got[i].status == 0
+        assert np.array_equal(np_u32(outs[i]).reshape(wants[i].shape), wants[i]), f"request {i}"
+    pir.pir_server_destroy(srv)
