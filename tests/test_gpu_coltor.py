@@ -54,6 +54,11 @@ CASES = [
     (8192, (1073692673,), 16, 2, 1, 2),
     (16384, (1073643521,), 16, 2, 1, 3),
     (32, Q108, 26, 5, 3, 1),
+    # the gadget's extremes: eight digits, and the widest base (z = 2^30)
+    (64, Q108, 14, 8, 2, 3),
+    (256, (synth.PRIMES_W32[0],), 30, 2, 2, 2),
+    # three limbs: blocks of 3 x N/16 threads
+    (512, Q108[:3], 22, 4, 1, 4),
 ]
 
 
