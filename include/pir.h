@@ -133,8 +133,9 @@ void pir_db_free(pir_db *db);
  *         with PIR_EINVAL instead)
  * out_dev: [B][2][D1][L][N]; must not overlap q_dev.
  * B = 0 is a no-op.  `path` must name a layout the DB holds (PIR_EINVAL
- * otherwise); PIR_PATH_AUTO picks the VALU kernels for small batches and
- * the INT8 MFMA kernels for large ones when both layouts exist. */
+ * otherwise); PIR_PATH_AUTO picks, when both layouts exist, the streaming
+ * VALU kernel for B <= 2 (B = 1 when a prime is 2^30 or more, where each
+ * client is its own pass over the DB) and the INT8 MFMA kernels above. */
 pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
                       uint32_t *out_dev, pir_path path, void *hip_stream);
 
