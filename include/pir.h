@@ -170,7 +170,9 @@ pir_status pir_rowsel_coeff(const pir_db *db, const uint32_t *q_coeff_dev, uint3
  *          pir_db_create, and L*N <= 16384 (the paper's N = 4096 with four
  *          limbs is the largest), else PIR_EUNSUPPORTED
  * ct_dev:  [B][2][ncols][L][N] NTT-domain residues < q_l (the layout of
- *          pir_rowsel's output)
+ *          pir_rowsel's output; larger values give unspecified results, and
+ *          PIR_VALIDATE=1 checks ct_dev and rgsw_dev and fails with
+ *          PIR_EINVAL instead)
  * rgsw_dev: [B][2][ell][2][L][N]: row (p, i) is the ciphertext pair that
  *          multiplies digit i of input polynomial p, NTT domain
  * out_dev: [B][2][(ncols+1)/2][L][N]; must overlap neither input.

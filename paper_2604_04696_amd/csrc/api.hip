@@ -411,6 +411,10 @@ pir_status pir_coltor_stage(const pir_params *ring, const uint32_t *ct, uint32_t
                      nout = (size_t)B * 2 * ((ncols + 1) / 2) * LN;
         PIR_REQUIRE(!overlaps(out, nout, ct, nct), "out overlaps ct");
         PIR_REQUIRE(!overlaps(out, nout, rgsw, nrg), "out overlaps rgsw");
+        if (env_flag("PIR_VALIDATE")) {
+            check_residues(ct, nct / 4, r, as_stream(stream));
+            check_residues(rgsw, nrg / 4, r, as_stream(stream));
+        }
         launch_coltor_stage(r, ct, B, ncols, rgsw, log2z, ell, out, as_stream(stream));
     });
 }

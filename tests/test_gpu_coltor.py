@@ -207,3 +207,23 @@ def test_coltor_decomposition_boundaries(pir, log2z, ell):
     pir.pir_coltor_stage(n, primes, to_dev(cts), B, ncols, to_dev(rg), log2z, ell, out)
     torch.cuda.synchronize()
     assert np.array_equal(np_u32(out).reshape(want.shape), want)
+
+
+def test_coltor_validate_rejects_non_residues(pir, monkeypatch):
+    # PIR_VALIDATE=1: a word >= its prime in ct or in the RGSW rows fails the
+    # call with PIR_EINVAL before any kernel of the stage runs
+    n, primes, log2z, ell, B, ncols = 64, Q108, 22, 5, 1, 2
+    monkeypatch.setenv("PIR_VALIDATE", "1")
+    cts = residues(311, (B, 2, ncols), primes, n)
+    rg = residues(312, (B, 2, ell, 2), primes, n)
+    out = empty_u32(B * 2 * 1 * len(primes) * n)
+    pir.pir_coltor_stage(n, primes, to_dev(cts), B, ncols, to_dev(rg), log2z, ell, out)   # valid: passes
+    torch.cuda.synchronize()
+    bad = cts.copy()
+    bad[0, 1, 1, 2, 17] = primes[2]
+    with pytest.raises(pir.PirError, match="PIR_VALIDATE"):
+        pir.pir_coltor_stage(n, primes, to_dev(bad), B, ncols, to_dev(rg), log2z, ell, out)
+    badr = rg.copy()
+    badr[0, 1, 4, 0, 3, 63] = 0xFFFFFFFF
+    with pytest.raises(pir.PirError, match="PIR_VALIDATE"):
+        pir.pir_coltor_stage(n, primes, to_dev(cts), B, ncols, to_dev(badr), log2z, ell, out)

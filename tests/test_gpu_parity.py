@@ -225,3 +225,22 @@ def test_kernel_timing_counts_main_kernels(pir):
     pir.pir_rowsel(db, q, out, path)    # not recorded once disabled
     torch.cuda.synchronize()
     assert pir.pir_kernel_time_read() == (0, 0.0)
+
+
+def test_rowsel_validate_rejects_non_residues(pir, monkeypatch):
+    # PIR_VALIDATE=1: a query word >= its prime fails with PIR_EINVAL on both
+    # paths; valid queries still run
+    n, primes, d0, d1, B = 64, synth.PRIMES_N4096, 12, 5, 2
+    monkeypatch.setenv("PIR_VALIDATE", "1")
+    coeffs = synth.db_coeffs(95, d0, d1, len(primes), n)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1))
+    pir.pir_db_load_ntt(db, to_dev(coeffs), domain=pir.PIR_DOMAIN_COEFF)
+    q = synth.query_uniform(96, B, d0, primes, n)
+    out = empty_u32(B * 2 * d1 * len(primes) * n)
+    bad = q.copy()
+    bad[1, 0, 7, 1, 33] = primes[1]
+    for path in (pir.PIR_PATH_VALU, pir.PIR_PATH_MFMA_I8):
+        pir.pir_rowsel(db, to_dev(q), out, path)
+        torch.cuda.synchronize()
+        with pytest.raises(pir.PirError, match="PIR_VALIDATE"):
+            pir.pir_rowsel(db, to_dev(bad), out, path)
