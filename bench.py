@@ -268,6 +268,25 @@ def q108_section(pir):
         res[name] = {"ms": round(ms, 3), "db_gbs": round(w.db_bytes / (ms * 1e-3) / 1e9, 1),
                      "mac_per_s": macs / (ms * 1e-3)}
         del q, out
+    # the path at the paper's parameters end to end: 32 clients' selector
+    # ciphertexts in the coefficient domain -> NTT + RowSel (MFMA) -> the first
+    # ColTor stage on its 512 output columns (gadget z = 2^22, ell = 5)
+    B, log2z, ell = w.clients, 22, 5
+    qc = torch.empty(B * 2 * w.d0 * w.slots, dtype=torch.int32, device="cuda")
+    pir.pir_synth_query(qc, synth.stream_key(w.seed, synth.TAG_QUERY, 3), 0, B, w.d0, w.primes, w.n)
+    rs = torch.empty(B * 2 * w.d1 * w.slots, dtype=torch.int32, device="cuda")
+    rg = torch.empty(B * 2 * ell * 2 * w.slots, dtype=torch.int32, device="cuda")
+    pir.pir_synth_query(rg, synth.stream_key(w.seed, synth.TAG_QUERY, 4), 0, B * ell * 2, 1, w.primes, w.n)
+    ct1 = torch.empty(B * 2 * (w.d1 // 2) * w.slots, dtype=torch.int32, device="cuda")
+
+    def pipeline():
+        pir.pir_rowsel_coeff(db, qc, rs, pir.PIR_PATH_MFMA_I8)
+        pir.pir_coltor_stage(w.n, w.primes, rs, B, w.d1, rg, log2z, ell, ct1)
+
+    pipeline()
+    torch.cuda.synchronize()
+    res["b32_coeff_rowsel_coltor1_ms"] = round(statistics.median(timed_calls(pipeline, 5)), 3)
+    del qc, rs, rg, ct1
     pir.pir_db_free(db)
     return res
 

@@ -87,6 +87,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "paper_2604_04696_amd.build.build() (there is no fallback)")
+        # torch's HIP runtime is loaded first so that libpir.so binds to it:
+        # the library takes torch's device memory and streams, and loading it
+        # ahead of torch left torch without a visible GPU
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -168,3 +169,14 @@ def test_coltor_stage_validation(n, primes, log2z, ell, status, frag):
     # B = 0 is a no-op once the parameters are valid
     if status == "PIR_EINVAL" and frag == "must not be NULL":
         assert pir.lib().pir_coltor_stage(ctypes.byref(ring), None, 0, 2, None, log2z, ell, None, None) == pir.PIR_OK
+
+
+def test_library_load_brings_torch_first():
+    # libpir.so must bind to torch's HIP runtime: loading the library imports
+    # torch before it (a fresh process, nothing imported beforehand)
+    code = ("import sys, paper_2604_04696_amd as p\n"
+            "assert 'torch' not in sys.modules\n"
+            "p.lib()\n"
+            "assert 'torch' in sys.modules\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
