@@ -72,6 +72,8 @@ def lib():
         L.oracle_ntt_inverse.restype = None
         L.oracle_ntt_forward_many.argtypes = [u64, u32, u64, u64, u32p, u32p, u64]
         L.oracle_ntt_forward_many.restype = None
+        L.oracle_ntt_inverse_many.argtypes = [u64, u32, u64, u64, u32p, u32p, u64]
+        L.oracle_ntt_inverse_many.restype = None
         L.oracle_negacyclic_mul.argtypes = [u64, u32, i64p, i64p, u32p]
         L.oracle_negacyclic_mul.restype = None
         L.oracle_rowsel.argtypes = [u32, u32, u32, u32, u32, u64p, u32p, u32p, u32p]
@@ -115,16 +117,15 @@ def ntt_forward(a: np.ndarray, q: int, psi_: int | None = None) -> np.ndarray:
 
 
 def ntt_inverse(ahat: np.ndarray, q: int, psi_: int | None = None) -> np.ndarray:
+    """Inverse of ntt_forward along the last axis (length N)."""
     ahat = np.ascontiguousarray(ahat, dtype=np.uint32)
     n = ahat.shape[-1]
     psi_ = psi(q, n) if psi_ is None else psi_
-    flat_in = ahat.reshape(-1, n)
-    out = np.empty_like(flat_in)
-    for i in range(flat_in.shape[0]):
-        row = np.ascontiguousarray(flat_in[i])
-        lib().oracle_ntt_inverse(int(q), n, int(psi_), _p(row, ctypes.c_uint32),
-                                 _p(out[i], ctypes.c_uint32))
-    return out.reshape(ahat.shape)
+    out = np.empty_like(ahat)
+    count = ahat.size // n
+    lib().oracle_ntt_inverse_many(int(q), n, int(psi_), count, _p(ahat, ctypes.c_uint32),
+                                  _p(out, ctypes.c_uint32), n)
+    return out
 
 
 def negacyclic_mul(a, b, q: int) -> np.ndarray:

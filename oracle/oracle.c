@@ -179,6 +179,15 @@ void oracle_ntt_forward_many(uint64_t q, uint32_t n, uint64_t psi, uint64_t coun
         oracle_ntt_forward(q, n, psi, a + (uint64_t)i * stride, out + (uint64_t)i * stride);
 }
 
+/* Batched inverse NTT over `count` contiguous length-n vectors (OpenMP). */
+void oracle_ntt_inverse_many(uint64_t q, uint32_t n, uint64_t psi, uint64_t count,
+                             const uint32_t *ahat, uint32_t *out, uint64_t stride)
+{
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < (int64_t)count; ++i)
+        oracle_ntt_inverse(q, n, psi, ahat + (uint64_t)i * stride, out + (uint64_t)i * stride);
+}
+
 /* Schoolbook product in Z_q[X]/(X^n + 1): X^n = -1. */
 void oracle_negacyclic_mul(uint64_t q, uint32_t n, const int64_t *a,
                            const int64_t *b, uint32_t *out)

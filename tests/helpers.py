@@ -1,7 +1,11 @@
 """Helpers shared by the GPU tests (inputs from ``synth``, expectations from
 ``oracle``; nothing here computes RowSel)."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
+import oracle
 import synth
 
 
@@ -42,3 +46,42 @@ def device_query(pir, B, d0, primes, n, seed, sub=0):
     q = empty_u32(B * 2 * d0 * len(primes) * n)
     pir.pir_synth_query(q, synth.stream_key(seed, synth.TAG_QUERY, sub), 0, B, d0, primes, n)
     return q
+
+
+# ---------------------------------------------------------------------------
+# full-size host inputs for the oracle (thread-parallel generation; numpy
+# releases the GIL inside its array operations)
+def _workers():
+    return max(1, min(16, os.cpu_count() or 4))
+
+
+def host_db_ntt(seed, d0, d1, primes, n, sub=0, log=None):
+    """The oracle's NTT-domain DB [D0][D1][L][N] for the seeded coefficients
+    that pir_synth_db_coeffs produces on the device: coefficients from
+    ``synth.db_coeffs`` in row blocks on a thread pool, then the oracle's own
+    NTT of every limb."""
+    L = len(primes)
+    coeffs = np.empty((d0, d1, L, n), dtype=np.uint32)
+    step = max(1, -(-d0 // (4 * _workers())))
+
+    def fill(r0):
+        r1 = min(d0, r0 + step)
+        coeffs[r0:r1] = synth.db_coeffs(seed, d0, d1, L, n, sub=sub, rows=np.arange(r0, r1))
+
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(fill, range(0, d0, step)))
+    if log:
+        log(f"oracle NTT of {d0} x {d1} x {L} polynomials (N = {n})")
+    return oracle.ntt_db(coeffs, primes)
+
+
+def host_query(seed, B, d0, primes, n, sub=0):
+    """synth.query_uniform for all B clients, clients generated in parallel."""
+    out = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
+
+    def fill(b):
+        out[b] = synth.query_uniform(seed, B, d0, primes, n, sub=sub, clients=[b])[0]
+
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(fill, range(B)))
+    return out
