@@ -139,6 +139,25 @@ void pir_db_free(pir_db *db);
 pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
                       uint32_t *out_dev, pir_path path, void *hip_stream);
 
+/* Allocation-free RowSel, for callers that cannot allocate device memory:
+ * code under hipGraph stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Computes exactly what pir_rowsel computes on the VALU
+ * path (the streaming kernel), bit for bit, for 1 <= B <= 4 clients against a
+ * DB holding the VALU layout; B = 0 is a no-op.  Its staging (the output's
+ * size: L*N*D1*2B*4 bytes, or L*N*D1*2*4 with a prime of 2^30 or more, where
+ * clients run one pass each) lives in a library-owned device array of
+ * PIR_NOALLOC_SCRATCH_BYTES per GPU, held from library load until the process
+ * ends; larger calls fail with PIR_EINVAL before anything is enqueued (e.g.
+ * N = 4096, L = 2, D1 = 512 allows B <= 2).  The call allocates nothing:
+ * no hipMalloc, no stream-ordered scratch, no events (kernel timing is not
+ * recorded, PIR_VALIDATE is not applied).  Every call on one GPU uses that
+ * GPU's one array: calls that overlap on a GPU (two streams, or two threads)
+ * race and give undefined output; calls ordered on one stream are safe.
+ * Arguments, layouts and stream semantics as for pir_rowsel. */
+#define PIR_NOALLOC_SCRATCH_BYTES (64u << 20)
+pir_status pir_rowsel_noalloc(const pir_db *db, const uint32_t *q_dev, uint32_t B,
+                              uint32_t *out_dev, void *hip_stream);
+
 /* RowSel on selector ciphertexts given in the coefficient domain, the form
  * query expansion produces them in (sec. 2.2): every query polynomial is
  * first taken to the NTT domain with the convention of pir_db_load_ntt

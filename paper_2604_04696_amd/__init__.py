@@ -57,6 +57,7 @@ SIGNATURES = {
     "pir_db_free": (None, [_vp]),
     "pir_rowsel": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
     "pir_rowsel_coeff": (_i32, [_vp, _vp, _u32, _vp, _i32, _vp]),
+    "pir_rowsel_noalloc": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "pir_rowsel_grouped": (_i32, [_vp, _u32, _i32, _vp]),
     "pir_coltor_stage": (_i32, [ctypes.POINTER(pir_params), _vp, _u32, _u32, _vp, _u32, _u32, _vp, _vp]),
     "pir_rowsel_grouped_tile": (_i32, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
@@ -218,6 +219,16 @@ def _rowsel_args(db: Db, query, out, B):
 def pir_rowsel(db: Db, query, out, path: int = PIR_PATH_AUTO, stream=None, B: int | None = None):
     qp, B, op = _rowsel_args(db, query, out, B)
     _check(lib().pir_rowsel(db.handle, qp, B, op, path, _stream(stream)), "pir_rowsel")
+
+
+def pir_rowsel_noalloc(db: Db, query, out, stream=None, B: int | None = None):
+    """Allocation-free RowSel (streaming VALU path, 1..4 clients, staging in
+    the library's fixed per-GPU array of PIR_NOALLOC_SCRATCH_BYTES)."""
+    qp, B, op = _rowsel_args(db, query, out, B)
+    _check(lib().pir_rowsel_noalloc(db.handle, qp, B, op, _stream(stream)), "pir_rowsel_noalloc")
+
+
+PIR_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def pir_rowsel_coeff(db: Db, query_coeff, out, path: int = PIR_PATH_AUTO, stream=None, B: int | None = None):

@@ -220,8 +220,12 @@ void launch_db_layout_mfma(const pir_db &db, const uint32_t *ntt_src, uint32_t r
                            uint32_t nrows, hipStream_t st);
 void launch_rowsel_valu(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st);
+// 2B <= 8.  stage_buf: staging of stream_staging_bytes(db, B) bytes supplied by
+// the caller (NULL: stream-ordered scratch, and the kernel is timed when
+// kernel timing is on)
 void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
-                          hipStream_t st);   // 2B <= 8
+                          hipStream_t st, void *stage_buf = nullptr);
+size_t stream_staging_bytes(const pir_db &db, uint32_t B);
 // q_coeff: the query is in the coefficient domain (transformed first)
 void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out,
                         hipStream_t st, bool q_coeff = false);

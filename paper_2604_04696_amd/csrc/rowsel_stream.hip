@@ -19,6 +19,7 @@
 // layout.  Storing into the boundary layout directly scatters one 16-byte
 // piece per lane over as many cache lines, and those partial-line writes,
 // interleaved with the DB stream, cost about a tenth of the kernel's time.
+#include <optional>
 #include <type_traits>
 
 #include "common.h"
@@ -178,7 +179,13 @@ stream_out_transpose_kernel(const uint4 *__restrict__ stage, uint4 *__restrict__
     }
 }
 
-void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, hipStream_t st) {
+size_t stream_staging_bytes(const pir_db &db, uint32_t B) {
+    const uint64_t rows_per_pass = db.wide ? 2u : 2ull * B;
+    return (size_t)db.slots() * rows_per_pass * db.p.d1 * 4;
+}
+
+void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, hipStream_t st,
+                          void *stage_buf) {
     const auto &p = db.p;
     const uint64_t groups = (uint64_t)p.nprimes * (p.n / 4);
     ModQ4s mods{};
@@ -198,14 +205,18 @@ void launch_rowsel_stream(const pir_db &db, const uint32_t *q, uint32_t B, uint3
     const uint64_t tblocks = nblk_c * ((groups + TR_G - 1) / TR_G);
     if (blocks >= (1ull << 31) || tblocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "grid too large");
 
-    StreamScratch scratch(groups * C * sizeof(uint4), st);   // [groups][rows][D1] vectors, reused per pass
-    uint4 *stage = scratch.as<uint4>();
+    // [groups][rows][D1] vectors, reused per pass: the caller's buffer, else stream-ordered scratch
+    StreamScratch scratch(stage_buf ? 0 : groups * C * sizeof(uint4), st);
+    uint4 *stage = stage_buf ? static_cast<uint4 *>(stage_buf) : scratch.as<uint4>();
     const uint64_t q_rows = (uint64_t)p.d0 * p.nprimes * p.n, o_rows = (uint64_t)p.d1 * p.nprimes * p.n;
     for (uint32_t pass = 0; pass < passes; ++pass) {
         const uint32_t *qp = q + pass * rows_per_pass * q_rows;
         uint32_t *op = out + pass * rows_per_pass * o_rows;
         {
-            KernelTimer::Scope timed(st);
+            // (no timing events around a launch into a caller's buffer: that
+            // form allocates nothing, events included)
+            std::optional<KernelTimer::Scope> timed;
+            if (!stage_buf) timed.emplace(st);
             dim3 grid((uint32_t)blocks), block(STREAM_THREADS);
             auto go = [&](auto wide) {
                 constexpr bool W = decltype(wide)::value;
