@@ -139,8 +139,17 @@ def grouped_section(pir, reps: int):
            "eager_ms": round(eager, 3), "graph_ms": round(graph, 3),
            "mac_per_s": macs / (graph * 1e-3), "db_gbs": round(dbb / (graph * 1e-3) / 1e9, 1),
            "launches": 2 * len(insts) + 1}
-    tm, tn = pir.pir_rowsel_grouped_tile(items)
-    res["tile"] = f"{tm}x{tn} (timed at plan build)"
+    tiles = pir.pir_rowsel_grouped_tiles(items)
+    res["tiles"] = [f"{p}x{m}x{n}" for p, m, n in tiles]   # points x rows x columns per instance
+    res["tile_note"] = "per instance, timed at plan build among the shapes within 25% of the fewest padded words"
+    # output words the GEMM computes (tile padding included) against the
+    # 2B x D1 it needs, per point and K row (query rows are padded to 32)
+    useful = computed = 0
+    for it, (p, m, n) in zip(insts, tiles):
+        mp = (2 * it.clients + 31) // 32 * 32
+        useful += 2 * it.clients * it.d1 * it.d0
+        computed += (mp + m - 1) // m * m * ((it.d1 + n - 1) // n * n) * it.d0
+    res["useful_over_computed"] = round(useful / computed, 3)
     del g
     for db, q, B, out in items:
         pir.pir_db_free(db)
@@ -212,6 +221,28 @@ def serving_section(pir, n_requests: int, loads):
     pir.pir_db_free(db)
     return {"workload": w.name, "capacity": cap, "chunks": chunks, "saturated_qps": round(qps_sat, 1),
             "runs": runs, "in_mix_equals_alone": same, "steps": st.steps}
+
+
+def peaks_section(pir):
+    """Measured ceilings on this GPU (include/pir_peak.h): INT8 MFMA issue
+    rate on zero and on changing operands (with the shader clock it ran at),
+    the v_mad_u64_u32 rate, and a streaming read of 4 GiB.  Second of two
+    runs each."""
+    import torch
+    res = {}
+    for name, rnd in (("mfma_i8_zero", False), ("mfma_i8_random", True)):
+        for _ in range(2):
+            tops, mhz = pir.pir_peak_mfma_i8(200_000, rnd)
+        res[name] = {"tops": round(tops, 1), "mhz": round(mhz)}
+    for _ in range(2):
+        gops, mhz = pir.pir_peak_valu_mad64(200_000)
+    res["valu_mad64"] = {"gops": round(gops, 1), "mhz": round(mhz)}
+    buf = torch.zeros(1 << 30, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        gbs = pir.pir_peak_hbm_read(buf)
+    res["hbm_read_gbs"] = round(gbs, 1)
+    del buf
+    return res
 
 
 def query_front_section(pir, db, w, q_ntt, out, ntt_domain_ms):
@@ -376,26 +407,47 @@ def make_query_sub(pir, w, sub):
 def cpu_baseline(w, target_s: float):
     """The oracle (unmodified) on a bounded sample of the headline workload:
     all 512 rows and all 8192 points of a subset of DB columns, one client,
-    repeated until about `target_s` seconds of oracle RowSel time."""
-    import numpy as np
+    repeated until about `target_s` seconds of oracle RowSel time on all host
+    threads; then the same sample on one thread, and the whole tiny workload
+    (N = 1024, 16 x 16, one client) on one thread."""
     import oracle
     import synth
+
+    def timed(fn, budget):
+        reps, t = 0, 0.0
+        while t < budget and reps < 1000:
+            t0 = time.perf_counter()
+            fn()
+            t += time.perf_counter() - t0
+            reps += 1
+        return reps, t
+
     cols = list(range(32))
     coeffs = synth.db_coeffs(w.dbseed, w.d0, w.d1, w.nprimes, w.n, cols=cols)
     dhat = oracle.ntt_db(coeffs, w.primes)
     q = synth.query_uniform(w.seed, 1, w.d0, w.primes, w.n)
-    reps, t = 0, 0.0
-    while t < target_s and reps < 1000:
-        t0 = time.perf_counter()
-        oracle.rowsel(q, dhat, w.primes)
-        t += time.perf_counter() - t0
-        reps += 1
-    db_bytes = w.slots * w.d0 * len(cols) * 4 * reps
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": db_bytes / t / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"RowSel of DB columns 0-{len(cols) - 1} (all {w.d0} rows, {w.slots} points, "
-                      f"1 client), repeated {reps}x, {t:.1f} s of oracle time",
-            "mac_per_s": w.slots * 2 * w.d0 * len(cols) * reps / t}
+    threads = oracle.max_threads()
+    reps, t = timed(lambda: oracle.rowsel(q, dhat, w.primes), target_s)
+    col_bytes = w.slots * w.d0 * len(cols) * 4
+    col_macs = w.slots * 2 * w.d0 * len(cols)
+    res = {"value": col_bytes * reps / t / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"RowSel of DB columns 0-{len(cols) - 1} (all {w.d0} rows, {w.slots} points, "
+                     f"1 client), repeated {reps}x, {t:.1f} s of oracle time",
+           "mac_per_s": col_macs * reps / t}
+    oracle.set_threads(1)
+    try:
+        reps1, t1 = timed(lambda: oracle.rowsel(q, dhat, w.primes), target_s / 2)
+        res["one_core"] = {"gbs": round(col_bytes * reps1 / t1 / 1e9, 3), "mac_per_s": col_macs * reps1 / t1,
+                           "sample": f"the same sample on one thread, {reps1}x, {t1:.1f} s"}
+        tw = synth.TINY
+        tq = synth.query_uniform(tw.seed, 1, tw.d0, tw.primes, tw.n)
+        tdb = oracle.ntt_db(synth.db_coeffs(tw.seed, tw.d0, tw.d1, tw.nprimes, tw.n), tw.primes)
+        repst, tt = timed(lambda: oracle.rowsel(tq, tdb, tw.primes), 1.0)
+        res["tiny_one_core"] = {"ms_per_call": round(tt / repst * 1e3, 4), "mac_per_s": tw.macs * repst / tt,
+                                "workload": tw.name}
+    finally:
+        oracle.set_threads(threads)
+    return res
 
 
 def main():
@@ -487,6 +539,9 @@ def main():
     del ref_src, ref_dst
     torch.cuda.empty_cache()
 
+    peaks = peaks_section(pir)
+    log(f"measured peaks: {peaks}")
+
     ms_step = wall / args.steps * 1e3
     db_gbs = w.db_bytes / (ms_step * 1e-3) / 1e9
     alg_bytes = w.db_bytes + w.io_bytes
@@ -510,7 +565,10 @@ def main():
                      "call_ms": round(call_ms, 4),
                      "alg_bytes_per_launch": alg_bytes,
                      "measured_copy_gbs": round(copy_gbs, 1),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4),
+                     "measured_read_gbs": peaks["hbm_read_gbs"],
+                     "frac_of_measured": round(achieved / peaks["hbm_read_gbs"], 4)},
+        "measured_peaks": peaks,
     }
 
     # ------------------------------------------------------------ batched
@@ -529,6 +587,12 @@ def main():
         m = res["mfma_i8"]
         m["i8_tops"] = round(wb.macs * 16 * 2 / (m["ms"] * 1e-3) / 1e12, 1)
         m["mfma_frac"] = round(m["i8_tops"] / I8_PEAK_TOPS, 4)
+        # against the measured MFMA loop on changing operands (the chip's
+        # attainable INT8 rate under load), and the VALU path against the
+        # measured v_mad_u64_u32 rate (one multiply-add per mod-MAC at least)
+        m["frac_of_measured"] = round(m["i8_tops"] / peaks["mfma_i8_random"]["tops"], 4)
+        v = res["valu"]
+        v["frac_of_measured_mad64"] = round(v["mac_per_s"] / (peaks["valu_mad64"]["gops"] * 1e9), 4)
         res["mfma_over_valu"] = round(res["valu"]["ms"] / m["ms"], 2)
         line["batched_b64"] = res
         line["query_front_b64"] = query_front_section(pir, db, wb, qb, ob, m["ms"])

@@ -123,7 +123,9 @@ pir_status pir_db_params(const pir_db *db, pir_params *out);
 uint32_t pir_db_layouts(const pir_db *db);
 
 /* Release a DB (NULL is a no-op).  Synchronises the device first and drops
- * every cached grouped-call plan. */
+ * the cached grouped-call plans whose item lists name this DB (a hipGraph
+ * that captured such a call must not be replayed afterwards; plans of other
+ * DBs, and graphs over them, are unaffected). */
 void pir_db_free(pir_db *db);
 
 /* RowSel for B clients against one DB (sec. 2.2, sec. 2.3, sec. 5.1.1):
@@ -215,32 +217,46 @@ typedef struct {
 
 /* Many RowSel instances of uneven shape (own DB, own batch) at once (the
  * counterpart of the paper's per-prime, N-chunked launches under CUDA
- * Graphs, sec. 5.2.2).  Every item must satisfy the pir_rowsel contract and
- * live on the current device; outputs of distinct items must not overlap one
- * another or any query.  Results equal `count` separate pir_rowsel calls bit
- * for bit.  MFMA path (PIR_PATH_MFMA_I8, or AUTO when every DB holds the MFMA
+ * Graphs, sec. 5.2.2, with the tile parameters of sec. 5.1.1 chosen per
+ * instance).  Every item must satisfy the pir_rowsel contract and live on
+ * the current device; outputs of distinct items must not overlap one another
+ * or any query.  Results equal `count` separate pir_rowsel calls bit for
+ * bit.  MFMA path (PIR_PATH_MFMA_I8, or AUTO when every DB holds the MFMA
  * layout): one query-ingest launch per item, ONE persistent GEMM launch over
  * the output tiles of all items, one output-transpose launch per item.  VALU
  * path: the items' RowSel launches back to back.
  * The first MFMA call for a given list of (db, B) allocates a plan (device
- * work table and scratch, kept for reuse; up to 8 plans are cached) and must
- * not be made while the stream is being captured (PIR_EINVAL); later calls
- * with the same list only enqueue kernels and may be captured into a
- * hipGraph, with any query/output pointers.  When the plan is built, both
- * output tile shapes of the persistent kernel (128 x 64 and 64 x 128) run
- * once on the call's inputs, timed on its stream (the first call therefore
- * synchronizes the stream), and the faster one is kept; PIR_MFMA_WM=4 or 2
- * in the environment forces one shape, PIR_AUTOTUNE=0 picks the shape that
- * pads fewer rows without timing. */
+ * work table and scratch, kept for reuse) and must not be made while the
+ * stream is being captured (PIR_EINVAL); later calls with the same list only
+ * enqueue kernels and may be captured into a hipGraph, with any query/output
+ * pointers.  Up to 8 plans that were never used under capture are cached
+ * (least recently used ones are released beyond that); a plan used under
+ * capture is kept until one of its DBs is freed, so a captured graph stays
+ * valid until pir_db_free of one of its items' DBs.
+ * Tiles: each item gets its own tile shape, `points` NTT points side by side
+ * x `rows` GEMM rows x `columns` DB columns, from 1 x 128x64, 1 x 64x128,
+ * 1 x 32x256, 1 x 256x32, 2 x 64x64, 2 x 32x128 and 2 x 128x32 (eight 32x32
+ * MFMA sub-tiles each).  When the plan is built, every item's shapes within
+ * 25% of the fewest padded output words run once, alone, on the call's own
+ * inputs, timed on its stream (the first call therefore synchronizes the
+ * stream), and the fastest is kept.  PIR_AUTOTUNE=0 in the environment keeps
+ * the shape with the fewest padded words without timing;
+ * PIR_GROUPED_SHAPE="points,rows,columns" forces one shape on every item.
+ * Two pipeline rings exist: three stages of 192 operand rows (the 1 x 128x64
+ * and 1 x 64x128 shapes) and two stages of 320 rows (every shape); the items
+ * of each ring run in one persistent launch (two GEMM launches at most), and
+ * the timing above covers both rings for the 192-row shapes.
+ * PIR_GROUPED_RING=deep or wide restricts the choice to one ring. */
 pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count,
                               pir_path path, void *hip_stream);
 
-/* Output tile (rows x columns of the GEMM) chosen for the cached MFMA plan of
- * an item list, as built by a previous pir_rowsel_grouped call with the
- * same list of (db, B).  Only the (db, B) pairs of `items` are read.
- * PIR_EINVAL if no plan exists for the list or an out pointer is NULL. */
-pir_status pir_rowsel_grouped_tile(const pir_rowsel_item *items, uint32_t count,
-                                   uint32_t *tile_m, uint32_t *tile_n);
+/* Tile shapes chosen for the cached MFMA plan of an item list, as built by a
+ * previous pir_rowsel_grouped call with the same list of (db, B): tiles[3i],
+ * tiles[3i+1], tiles[3i+2] = points, rows, columns of item i (zeros for an
+ * item with B = 0).  Only the (db, B) pairs of `items` are read; `tiles`
+ * holds 3*count words.  PIR_EINVAL if no plan exists for the list or a
+ * pointer is NULL. */
+pir_status pir_rowsel_grouped_tiles(const pir_rowsel_item *items, uint32_t count, uint32_t *tiles);
 
 /* ---------------------------------------------------------------- serving */
 /* A RowSel server over one resident DB with continuous batching.  The DB's
@@ -259,7 +275,9 @@ typedef struct {
     uint32_t max_clients;   /* admission cap (slots), 1..4096; 0 = 256 */
     uint32_t chunks;        /* sweep steps per pass over the DB, 1..L*N/4; 0 = 16 */
     uint32_t pipeline;      /* steps kept in flight on the device, 1..4; 0 = 2 */
-    uint32_t reserved;
+    uint32_t max_waiting;   /* requests that may wait for a slot; an arrival that
+                               finds this many waiting completes at once with
+                               PIR_EBUSY (others go on); 0 = no bound */
     uint64_t hbm_budget;    /* device bytes the server may allocate; 0 = 90% of the
                                free memory at creation.  Admission capacity is the
                                number of client slots (64 MiB per client at
@@ -268,9 +286,16 @@ typedef struct {
 } pir_server_opts;
 
 typedef struct {
-    uint64_t id;               /* caller's tag, echoed in the completion */
+    uint64_t id;               /* caller's tag, echoed in the completion; unique among
+                                  the live (submitted, not yet returned) requests */
     const uint32_t *q_dev;     /* [2][D0][L][N] one client's selectors (residues < q_l) */
     uint32_t *out_dev;         /* [2][D1][L][N]; must not overlap another live request's */
+    void *ready_event;         /* hipEvent_t recorded after the work that writes q_dev,
+                                  on the producer's stream; the server's reads of the
+                                  query are ordered after it (hipStreamWaitEvent at
+                                  submission, so the event may be reused once the call
+                                  returns).  NULL: q_dev is already complete on the
+                                  device when pir_serve_step is called */
 } pir_request;
 
 typedef struct {
@@ -298,12 +323,17 @@ pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_
 
 /* One turn of the serving loop; never blocks on the device.  Queues the
  * `n_arrivals` requests (stamped t_submit = now; a malformed request completes
- * at once with PIR_EINVAL), retires finished steps, admits waiting requests
- * into free slots in arrival order, and launches steps until `pipeline` are
- * in flight (none while no client is admitted).  Copies up to `cap` finished
- * requests, oldest first, into `done` and sets *n_done; the rest are kept for
- * the next call.  The caller keeps each request's buffers alive until its
- * completion is returned.  Not thread safe: one caller per server. */
+ * at once with PIR_EINVAL, one that finds `max_waiting` requests waiting with
+ * PIR_EBUSY), retires finished steps, admits waiting requests into free slots
+ * in arrival order, and launches steps until `pipeline` are in flight (none
+ * while no client is admitted).  Copies up to `cap` finished requests, oldest
+ * first, into `done` and sets *n_done; the rest are kept for the next call.
+ * The caller keeps each request's buffers alive until its completion is
+ * returned.  An arrival whose id equals that of a live request (or of another
+ * arrival of the same call) fails the whole call with PIR_EINVAL before
+ * anything is queued.  Admission capacity is fixed when the server is
+ * created (hbm_budget); requests beyond it wait.  Not thread safe: one caller
+ * per server. */
 pir_status pir_serve_step(pir_server *srv, const pir_request *arrivals, uint32_t n_arrivals,
                           pir_completion *done, uint32_t cap, uint32_t *n_done);
 

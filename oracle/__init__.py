@@ -78,6 +78,10 @@ def lib():
         L.oracle_negacyclic_mul.restype = None
         L.oracle_rowsel.argtypes = [u32, u32, u32, u32, u32, u64p, u32p, u32p, u32p]
         L.oracle_rowsel.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -160,3 +164,12 @@ def rowsel(query: np.ndarray, db: np.ndarray, primes) -> np.ndarray:
     lib().oracle_rowsel(B, D0, D1, L, N, _p(pr, ctypes.c_uint64), _p(query, ctypes.c_uint32),
                         _p(db, ctypes.c_uint32), _p(out, ctypes.c_uint32))
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

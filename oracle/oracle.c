@@ -26,6 +26,7 @@
  * Parity pins for every function live in the CPU test suite (direct O(N^2)
  * evaluation, Python big-integer products, closed forms, toy encryption).
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -237,3 +238,8 @@ void oracle_rowsel(uint32_t B, uint32_t D0, uint32_t D1, uint32_t L, uint32_t N,
         free(acc);
     }
 }
+
+/* ------------------------------------------------------------ threading */
+/* Threads the OpenMP loops above use (for timing the oracle on one core). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }

@@ -1,4 +1,4 @@
-"""Python binding of libpir.so (include/pir.h, include/pir_synth.h).
+"""Python binding of libpir.so (include/pir.h, include/pir_synth.h, include/pir_peak.h).
 
 Argument marshalling only: every step of RowSel runs in the HIP library.
 Tensors are torch device tensors (int32 or uint32, contiguous) whose data
@@ -60,7 +60,7 @@ SIGNATURES = {
     "pir_rowsel_noalloc": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "pir_rowsel_grouped": (_i32, [_vp, _u32, _i32, _vp]),
     "pir_coltor_stage": (_i32, [ctypes.POINTER(pir_params), _vp, _u32, _u32, _vp, _u32, _u32, _vp, _vp]),
-    "pir_rowsel_grouped_tile": (_i32, [_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    "pir_rowsel_grouped_tiles": (_i32, [_vp, _u32, ctypes.POINTER(_u32)]),
     "pir_clock": (ctypes.c_double, []),
     "pir_server_create": (_i32, [_vp, _vp, ctypes.POINTER(_vp)]),
     "pir_serve_step": (_i32, [_vp, _vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]),
@@ -72,6 +72,10 @@ SIGNATURES = {
     "pir_kernel_time_read": (_i32, [ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_double)]),
     "pir_last_error": (ctypes.c_char_p, []),
     "pir_version": (ctypes.c_char_p, []),
+    "pir_peak_mfma_i8": (_i32, [_u32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                _vp]),
+    "pir_peak_valu_mad64": (_i32, [_u32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _vp]),
+    "pir_peak_hbm_read": (_i32, [_vp, _u64, ctypes.POINTER(ctypes.c_double), _vp]),
     "pir_synth_query": (_i32, [_vp, _u64, _u32, _u32, _u32, _u32, _u32,
                                ctypes.POINTER(_u32), _vp]),
     "pir_synth_db_coeffs": (_i32, [_vp, _u64, _u32, _u32, _u32, _u32, _u32, _vp]),
@@ -271,25 +275,26 @@ def pir_rowsel_grouped(items, path: int = PIR_PATH_AUTO, stream=None):
                                     _stream(stream)), "pir_rowsel_grouped")
 
 
-def pir_rowsel_grouped_tile(items):
-    """(rows, cols) of the output tile kept for the plan of this item list."""
+def pir_rowsel_grouped_tiles(items):
+    """[(points, rows, cols)] of the tile kept for each item of the plan of
+    this item list ((0, 0, 0) for B = 0 items)."""
     arr = (pir_rowsel_item * max(1, len(items)))()
     for i, (db, q, B, out) in enumerate(items):
         arr[i].db, arr[i].B = db.handle, B
-    tm, tn = _u32(), _u32()
-    _check(lib().pir_rowsel_grouped_tile(ctypes.cast(arr, ctypes.c_void_p), len(items), ctypes.byref(tm),
-                                         ctypes.byref(tn)), "pir_rowsel_grouped_tile")
-    return tm.value, tn.value
+    t = (_u32 * max(3, 3 * len(items)))()
+    _check(lib().pir_rowsel_grouped_tiles(ctypes.cast(arr, ctypes.c_void_p), len(items), t),
+           "pir_rowsel_grouped_tiles")
+    return [(t[3 * i], t[3 * i + 1], t[3 * i + 2]) for i in range(len(items))]
 
 
 # ---------------------------------------------------------------- serving
 class pir_server_opts(ctypes.Structure):
-    _fields_ = [("max_clients", _u32), ("chunks", _u32), ("pipeline", _u32), ("reserved", _u32),
+    _fields_ = [("max_clients", _u32), ("chunks", _u32), ("pipeline", _u32), ("max_waiting", _u32),
                 ("hbm_budget", _u64)]
 
 
 class pir_request(ctypes.Structure):
-    _fields_ = [("id", _u64), ("q_dev", _vp), ("out_dev", _vp)]
+    _fields_ = [("id", _u64), ("q_dev", _vp), ("out_dev", _vp), ("ready_event", _vp)]
 
 
 class pir_completion(ctypes.Structure):
@@ -321,8 +326,8 @@ class Server:
 
 
 def pir_server_create(db: Db, max_clients: int = 0, chunks: int = 0, pipeline: int = 0,
-                      hbm_budget: int = 0) -> Server:
-    o = pir_server_opts(max_clients, chunks, pipeline, 0, hbm_budget)
+                      hbm_budget: int = 0, max_waiting: int = 0) -> Server:
+    o = pir_server_opts(max_clients, chunks, pipeline, max_waiting, hbm_budget)
     h = _vp()
     _check(lib().pir_server_create(db.handle, ctypes.byref(o), ctypes.byref(h)), "pir_server_create")
     return Server(h.value, db)
@@ -330,18 +335,31 @@ def pir_server_create(db: Db, max_clients: int = 0, chunks: int = 0, pipeline: i
 
 def pir_serve_step(srv: Server, arrivals=(), cap: int = 1024):
     """arrivals: iterable of (id, query tensor [2][D0][L][N], out tensor [2][D1][L][N]).
+    The server's reads of each query are ordered after the work enqueued so
+    far on torch's current stream (an event recorded there).  Request ids
+    must be unique among live requests (ValueError otherwise).
     Returns the list of finished pir_completion records."""
+    import torch
     arrivals = list(arrivals)
+    ids = [rid for rid, _, _ in arrivals]
+    if len(set(ids)) != len(ids) or any(rid in srv.live for rid in ids):
+        raise ValueError("pir_serve_step: a request id is already live")
+    ready = None
+    if arrivals:
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream())
     arr = (pir_request * max(1, len(arrivals)))()
     for i, (rid, q, out) in enumerate(arrivals):
         _need_u32(q, "query")
         _need_u32(out, "out")
         arr[i].id, arr[i].q_dev, arr[i].out_dev = rid, _ptr(q, "query"), _ptr(out, "out")
-        srv.live[rid] = (q, out)
+        arr[i].ready_event = ready.cuda_event
     done = (pir_completion * max(1, cap))()
     nd = _u32()
     _check(lib().pir_serve_step(srv.handle, ctypes.cast(arr, _vp), len(arrivals), ctypes.cast(done, _vp), cap,
                                 ctypes.byref(nd)), "pir_serve_step")
+    for rid, q, out in arrivals:
+        srv.live[rid] = (q, out)
     res = [done[i] for i in range(nd.value)]
     for c in res:
         srv.live.pop(c.id, None)
@@ -422,3 +440,29 @@ def pir_synth_draw(out, key: int, i0: int, stream=None):
         raise TypeError("out must be int64/uint64")
     _check(lib().pir_synth_draw(_ptr(out, "out"), key, i0, out.numel(), _stream(stream)),
            "pir_synth_draw")
+
+
+# ------------------------------------------------------------- pir_peak.h
+def pir_peak_mfma_i8(iters: int, random_operands: bool, stream=None):
+    """(TOP/s, MHz) of a register-only v_mfma_i32_32x32x32_i8 loop."""
+    t, m = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pir_peak_mfma_i8(iters, 1 if random_operands else 0, ctypes.byref(t), ctypes.byref(m),
+                                  _stream(stream)), "pir_peak_mfma_i8")
+    return t.value, m.value
+
+
+def pir_peak_valu_mad64(iters: int, stream=None):
+    """(G multiply-adds/s, MHz) of a v_mad_u64_u32 loop."""
+    g, m = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pir_peak_valu_mad64(iters, ctypes.byref(g), ctypes.byref(m), _stream(stream)),
+           "pir_peak_valu_mad64")
+    return g.value, m.value
+
+
+def pir_peak_hbm_read(src, stream=None):
+    """GB/s of a streaming read of the device tensor `src`."""
+    g = ctypes.c_double()
+    nbytes = src.numel() * src.element_size()
+    _check(lib().pir_peak_hbm_read(_ptr(src, "src"), nbytes, ctypes.byref(g), _stream(stream)),
+           "pir_peak_hbm_read")
+    return g.value

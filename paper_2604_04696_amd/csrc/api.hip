@@ -329,7 +329,7 @@ void pir_db_free(pir_db *db) {
     try {
         DeviceGuard dg(db->device);
         (void)hipDeviceSynchronize();
-        release_group_plans();
+        release_group_plans(db);
     } catch (...) {
     }
     dev_free(db->valu.data);
@@ -468,12 +468,10 @@ pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count, pir_
     });
 }
 
-pir_status pir_rowsel_grouped_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *tile_m,
-                                   uint32_t *tile_n) {
+pir_status pir_rowsel_grouped_tiles(const pir_rowsel_item *items, uint32_t count, uint32_t *tiles) {
     return guarded([&] {
-        PIR_REQUIRE(tile_m != nullptr && tile_n != nullptr, "NULL argument");
-        PIR_REQUIRE(count == 0 || items != nullptr, "items is NULL");
-        PIR_REQUIRE(group_plan_tile(items, count, tile_m, tile_n), "no grouped plan for this item list");
+        PIR_REQUIRE(tiles != nullptr && (count == 0 || items != nullptr), "NULL argument");
+        PIR_REQUIRE(group_plan_tiles(items, count, tiles), "no grouped plan for this item list");
     });
 }
 

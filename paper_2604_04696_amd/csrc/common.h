@@ -239,9 +239,11 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
                          const uint32_t *rgsw, uint32_t log2z, uint32_t ell, uint32_t *out, hipStream_t st);
 size_t mfma_query_scratch_bytes(const pir_db &db, uint32_t B);
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st);
-void release_group_plans();
-// Tile (rows x columns) of the cached grouped plan of an item set; false if none.
-bool group_plan_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *bm, uint32_t *bn);
+// Drops every cached grouped plan whose item list names `db`.
+void release_group_plans(const pir_db *db);
+// Tile of every item of the cached grouped plan of an item set, as (points,
+// rows, columns) triples (zeros for B = 0 items); false if there is no plan.
+bool group_plan_tiles(const pir_rowsel_item *items, uint32_t count, uint32_t *tiles);
 void check_rowsel_args(const pir_db *db, const uint32_t *q, uint32_t B, const uint32_t *out);
 void rowsel_one(const pir_db &db, const uint32_t *q, uint32_t B, uint32_t *out, pir_path path,
                 hipStream_t st, bool q_coeff = false);

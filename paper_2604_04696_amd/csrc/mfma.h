@@ -25,7 +25,10 @@ struct MfmaJob {
     uint32_t m_rows, mp, d1, nkc, L, N;
     uint32_t mstride;      // rows of a query plane (>= mp)
     uint32_t g_begin;      // first point group (groups of four points) of this job
-    uint32_t wm;           // waves along m: 4 (128 x 64 tiles) or 2 (64 x 128 tiles)
+    uint32_t wm;           // waves along m: 4 (128 x 64 tiles) or 2 (64 x 128 tiles); in
+                           // grouped launches 1, 2, 4 or 8 (see pts)
+    uint32_t pts;          // grouped launches: points a tile computes side by side (1 or 2);
+                           // the tile is pts x 32wm x 32wn with pts * wm * wn = 8 waves
     uint32_t nblk_m, nblk_n, groups, tile0, tiles;
     uint32_t split;        // recombination variant of the job's primes (RECOMB_*)
     uint32_t sstride;      // staging row stride: d1 rounded up to a multiple of 4 (16-byte rows)
@@ -38,6 +41,15 @@ MfmaJob make_mfma_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_
 uint32_t pick_wm(uint32_t B);
 void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
                       hipStream_t st);
+// The tile-shape-per-job kernel (grouped launches and serving steps): one
+// job by value (jobs_dev == NULL) or a device table of njobs jobs sorted by
+// tile0; `split` is the recombination variant every job of the launch takes.
+// deep: the three-stage 192-row ring (only the 1 x 128x64 and 1 x 64x128
+// shapes), else the two-stage 320-row ring (every shape).
+void launch_mfma_grouped(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
+                         uint32_t split, bool deep, hipStream_t st);
+// A job for that kernel in tile shape pts x 32wm x 32wn (pts * wm * wn = 8).
+MfmaJob make_shaped_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t B, uint32_t pts, uint32_t wm);
 // Staging row stride of a DB with d1 columns (16-byte aligned rows).
 inline uint32_t staging_stride(uint32_t d1) { return (d1 + 3) / 4 * 4; }
 

@@ -22,6 +22,7 @@
 // GEMM rows are computed and never transposed out).
 #include <algorithm>
 #include <list>
+#include <memory>
 #include <mutex>
 #include <vector>
 #include <type_traits>
@@ -655,6 +656,349 @@ void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njob
     PIR_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------ grouped GEMM, a tile shape per job
+// The tile of a grouped job is `pts` points side by side x BM rows x BN
+// columns, BM = 32 wm, BN = 32 wn, with pts * wm * wn = 8: every wave owns
+// one 32 x 32 sub-tile of one point, so a job whose output is narrow (few
+// clients, few DB columns) still keeps all eight waves on useful sub-tiles
+// (shapes: 1 x 128x64, 1 x 64x128, 1 x 32x256, 1 x 256x32, 2 x 64x64,
+// 2 x 32x128, 2 x 128x32).  A pipeline stage holds the operand rows of all
+// points of the tile, pts * (BM + BN) <= 320 rows of four digit planes
+// (80 KiB), in two stages (the whole 160 KiB of LDS); stage layout per point:
+// [4 digits][BM query rows][64] then [4 digits][BN DB rows][64], points one
+// after the other, so 16-row load unit u of a stage sits at byte u * 1024.
+// The rest (XCD-aware persistent tile order, seven class accumulators, exact
+// recombination, staging stores) is as in rowsel_mfma_persistent.
+//
+// The ring is a template (stage count and rows); the build uses two stages
+// of 320 rows.  With more than two stages every shape of the ring must load
+// the same number of 16-row units per wave, the fixed wait count of a step.
+// (A three-stage 192-row ring of this kernel, holding only the 128x64 and
+// 64x128 shapes, ran 5-20% slower than rowsel_mfma_persistent with the same
+// shapes -- its per-unit run-time guards and address selects are scalar
+// instructions, which the eight waves of a CU share one unit for -- so the
+// 192-row shapes run in that kernel instead, see launch_mfma_grouped.)
+template <int NST, int ROWS>
+struct GRing {
+    static constexpr int NST_ = NST;
+    static constexpr int STAGE_BYTES = 4 * ROWS * KCH;
+    static constexpr int LPW = (4 * ROWS / 16) / NWAVE;   // 16-row load units per wave at most
+    static_assert(LPW * NWAVE * 16 == 4 * ROWS, "load units must divide among the waves");
+    static_assert(NST * STAGE_BYTES <= 160 * 1024, "ring exceeds the LDS");
+};
+using RingWide = GRing<2, 320>;
+
+struct GTile {
+    const int8_t *qd, *dbd;
+    uint32_t *out;
+    uint32_t mp, mstride, d1, sstride, nkc, N, pts, bm, bn, wn, l, g, m0, n0, job, gl;
+};
+
+__device__ __forceinline__ GTile decode_gtile(uint32_t T, const MfmaJob &J, uint32_t j) {
+    const uint32_t loc = T - J.tile0;
+    const uint32_t tiles = J.nblk_m * J.nblk_n;
+    uint32_t gg = loc / tiles;
+    const uint32_t tile = loc % tiles;
+    GTile t;
+    t.gl = gg;
+    gg += J.g_begin;
+    t.qd = J.qd;
+    t.dbd = J.dbd;
+    t.out = J.out;
+    t.mp = J.mp;
+    t.mstride = J.mstride;
+    t.d1 = J.d1;
+    t.sstride = J.sstride;
+    t.nkc = J.nkc;
+    t.N = J.N;
+    t.pts = J.pts;
+    t.bm = 32 * J.wm;
+    t.wn = NWAVE / (J.pts * J.wm);
+    t.bn = 32 * t.wn;
+    const uint32_t G = J.N / 4;
+    t.l = gg / G;
+    t.g = gg % G;
+    t.m0 = (tile / J.nblk_n) * t.bm;
+    t.n0 = (tile % J.nblk_n) * t.bn;
+    t.job = j;
+    return t;
+}
+
+// Load side for one wave: unit u = wave + 8 i (i < n) of each stage, the
+// per-step advance of each unit's address (one query or DB plane chunk), and
+// the jump to the next set of pts points after the last k chunk.
+template <int G_LPW>
+struct GLoadCursor {
+    const int8_t *src[G_LPW];
+    uint64_t qadv, dadv;   // bytes of one query / DB plane chunk
+    uint32_t qmask;        // bit i: unit i reads a query plane
+    uint32_t n, kc, s, nkc, nsets, pts;
+
+    __device__ __forceinline__ uint64_t adv(int i) const { return (qmask >> i) & 1u ? qadv : dadv; }
+
+    __device__ __forceinline__ void start(const GTile &t, uint32_t wv, uint32_t lane) {
+        const uint64_t p0 = (uint64_t)t.l * t.N + 4 * t.g;
+        const uint64_t qplane = (uint64_t)t.mstride * KCH, dplane = (uint64_t)t.d1 * KCH;
+        const uint32_t upp = (t.bm + t.bn) / 4;   // units per point
+        n = t.pts * upp / NWAVE;
+        kc = s = 0;
+        nkc = t.nkc;
+        pts = t.pts;
+        nsets = 4 / t.pts;
+        const uint32_t lrow = lane / 4, lchunk = lane % 4;
+        qadv = qplane;
+        dadv = dplane;
+        qmask = 0;
+#pragma unroll
+        for (int i = 0; i < G_LPW; ++i) {
+            const uint32_t u = wv + NWAVE * i;
+            const uint32_t pt = u / upp;
+            uint32_t v = u % upp;
+            const bool q = v < t.bm / 4;
+            if (!q) v -= t.bm / 4;
+            const uint32_t rbn = q ? t.bm / 16 : t.bn / 16;
+            const uint32_t d = v / rbn, r = (v % rbn) * 16 + lrow;
+            const uint32_t row = q ? min(t.m0 + r, t.mp - 1) : min(t.n0 + r, t.d1 - 1);
+            const uint64_t plane = q ? qplane : dplane;
+            const int8_t *base = (q ? t.qd : t.dbd) + ((p0 + pt) * 4 + d) * t.nkc * plane;
+            src[i] = base + (uint64_t)row * KCH + 16 * (lchunk ^ swz(r));
+            qmask |= (q ? 1u : 0u) << i;
+        }
+    }
+
+    // Issues this wave's loads of the current step into `stage` (LDS
+    // addresses are wave-uniform: unit u lands at stage + u * 1024); returns
+    // true when the tile's last step has been issued.
+    __device__ __forceinline__ bool issue(int8_t *stage, uint32_t wv) {
+#pragma unroll
+        for (int i = 0; i < G_LPW; ++i) {
+            if (i < (int)n) {
+                const int8_t *from = src[i];
+                __builtin_amdgcn_global_load_lds(
+                    from, (__attribute__((address_space(3))) void *)(stage + (wv + NWAVE * i) * 1024), 16, 0, 0);
+                src[i] += adv(i);
+            }
+        }
+        if (++kc == nkc) {
+            kc = 0;
+            // the next set of points: pts points on, digit 0, k chunk 0
+#pragma unroll
+            for (int i = 0; i < G_LPW; ++i)
+                if (i < (int)n) src[i] += (uint64_t)(4 * pts - 1) * nkc * adv(i);
+            if (++s == nsets) return true;
+        }
+        return false;
+    }
+};
+
+// A single job travels by value in `one` (ONE = true: serving steps, whose
+// job changes every step); a grouped launch passes a device array of jobs
+// sorted by tile0.
+template <bool ONE, int MODE, class RING>
+__global__ void __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
+rowsel_mfma_grouped_kernel(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint32_t njobs,
+                           uint32_t total_tiles) {
+    constexpr int G_NSTAGE = RING::NST_, G_STAGE_BYTES = RING::STAGE_BYTES, G_LPW = RING::LPW;
+    __shared__ __attribute__((aligned(1024))) int8_t lds[G_NSTAGE * G_STAGE_BYTES];
+    auto decode = [&](uint32_t T) {
+        uint32_t j = 0;
+        if (!ONE)
+            while (j + 1 < njobs && T >= jobs[j + 1].tile0) ++j;
+        return decode_gtile(T, ONE ? one : jobs[j], j);
+    };
+
+    const uint32_t tid = threadIdx.x, lane = tid % 64;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid / 64);
+    const uint32_t per_xcd = gridDim.x / 8;
+    const uint32_t xcd = blockIdx.x % 8, yi = blockIdx.x / 8;
+    auto tile_index = [&](uint32_t i) { return (i * 8 + xcd) * per_xcd + yi; };
+    const uint32_t half = lane / 32;
+
+    // ---- load cursor
+    uint32_t li = 0;
+    bool l_done = tile_index(0) >= total_tiles;
+    GTile lt{};
+    GLoadCursor<G_LPW> lc;
+    lc.n = 0;
+    if (!l_done) {
+        lt = decode(tile_index(0));
+        lc.start(lt, wv, lane);
+    }
+    uint32_t lbuf = 0;
+    auto issue_next = [&]() {
+        const bool tile_end = lc.issue(lds + lbuf * G_STAGE_BYTES, wv);
+        lbuf = lbuf + 1 == G_NSTAGE ? 0 : lbuf + 1;
+        if (tile_end) {
+            ++li;
+            l_done = tile_index(li) >= total_tiles;
+            if (!l_done) {
+                lt = decode(tile_index(li));
+                lc.start(lt, wv, lane);
+            }
+        }
+    };
+
+    // ---- compute cursor
+    uint32_t ci = 0, s = 0, kc = 0, cbuf = 0;
+    bool c_done = l_done;
+    GTile ct = lt;
+    uint32_t wmi = 0, wni = 0, ptw = 0, abase = 0, bbase = 0, a_stride = 0, b_stride = 0;
+    bool active = false;
+    uint32_t achunk[2], bchunk[2];
+    auto start_compute = [&]() {
+        const uint32_t wpp = NWAVE / ct.pts;   // waves per point
+        ptw = wv / wpp;
+        const uint32_t r = wv % wpp;
+        wmi = r / ct.wn;
+        wni = r % ct.wn;
+        active = ct.m0 + wmi * 32 < ct.mp && ct.n0 + wni * 32 < ct.d1;
+        a_stride = ct.bm * KCH;
+        b_stride = ct.bn * KCH;
+        const uint32_t pbase = ptw * (ct.bm + ct.bn) * 4 * KCH;
+        abase = pbase + (wmi * 32 + lane % 32) * KCH;
+        bbase = pbase + 4 * a_stride + (wni * 32 + lane % 32) * KCH;
+        const uint32_t ar = wmi * 32 + lane % 32, br = wni * 32 + lane % 32;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            achunk[ks] = 16 * ((2 * ks + half) ^ swz(ar));
+            bchunk[ks] = 16 * ((2 * ks + half) ^ swz(br));
+        }
+    };
+    if (!c_done) start_compute();
+
+    i32x16 acc[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
+    uint32_t res[16];
+
+    uint32_t outstanding = 0;   // steps issued beyond the one being computed
+    for (int k = 0; k < G_NSTAGE - 1 && !l_done; ++k) {
+        issue_next();
+        ++outstanding;
+    }
+
+    bool after_store = false;
+    while (!c_done) {
+        // this step's operands are in once at most the later steps' loads
+        // are outstanding (every wave issues G_LPW units per step in a
+        // three-stage ring; after output stores, or near the end, wait for
+        // everything)
+        --outstanding;
+        if (G_NSTAGE > 2 && !after_store && outstanding == G_NSTAGE - 2) wait_vmcnt<(G_NSTAGE - 2) * G_LPW>();
+        else wait_vmcnt<0>();
+        after_store = false;
+        block_barrier();
+
+        const int8_t *abuf = lds + cbuf * G_STAGE_BYTES + abase, *bbuf = lds + cbuf * G_STAGE_BYTES + bbase;
+        i32x4 a[2][4], b[2][4];
+        auto read_frags = [&](int ks) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                a[ks][d] = *reinterpret_cast<const i32x4 *>(abuf + d * a_stride + achunk[ks]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                b[ks][d] = *reinterpret_cast<const i32x4 *>(bbuf + d * b_stride + bchunk[ks]);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto mfma_group = [&](int ks, int j) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ks][i], b[ks][j], acc[i + j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        if (active) {
+            read_frags(0);
+            mfma_group(0, 0);
+        }
+        // the next step's loads go to the stage every wave finished reading
+        // before this step's barrier
+        if (!l_done) {
+            issue_next();
+            ++outstanding;
+        }
+        if (active) {
+            read_frags(1);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) mfma_group(0, j);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mfma_group(1, j);
+        }
+        cbuf = cbuf + 1 == G_NSTAGE ? 0 : cbuf + 1;
+        const bool last = kc + 1 == ct.nkc;
+        if (last || ((kc + 1) * KCH) % KSUPER == 0) {
+            const EpiQ mq = ONE ? one.q[ct.l] : jobs[ct.job].q[ct.l];
+            const bool first = kc + 1 <= KSUPER / KCH;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int gr[7];
+#pragma unroll
+                for (int c = 0; c < 7; ++c) gr[c] = acc[c][r];
+                const uint32_t part = combine_classes<MODE>(gr, mq);
+                res[r] = first ? part : MODE == RECOMB_WIDE ? add_mod_w(res[r], part, mq.q)
+                                                            : add_mod(res[r], part, mq.q);
+            }
+#pragma unroll
+            for (int c = 0; c < 7; ++c) acc[c] = (i32x16){};
+            if (last) {
+                const uint32_t n = ct.n0 + wni * 32 + lane % 32;
+                if (active && n < ct.d1) {
+                    const uint32_t point = 4 * ct.gl + s * ct.pts + ptw;
+                    uint32_t *pt = ct.out + (uint64_t)point * ct.mp * ct.sstride + n;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t m = ct.m0 + wmi * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                        __builtin_nontemporal_store(res[r], pt + (uint64_t)m * ct.sstride);
+                    }
+                }
+                after_store = true;
+            }
+        }
+        if (++kc == ct.nkc) {
+            kc = 0;
+            if (++s == 4 / ct.pts) {
+                s = 0;
+                ++ci;
+                c_done = tile_index(ci) >= total_tiles;
+                if (!c_done) {
+                    ct = decode(tile_index(ci));
+                    start_compute();
+                }
+            }
+        }
+    }
+}
+
+// One persistent block per CU, over the tiles of a device job table
+// (jobs_dev, njobs) or of the single job `one` (jobs_dev == NULL).
+// deep: the jobs are 1 x 128x64 or 1 x 64x128 tiles (all the same) and run
+// in rowsel_mfma_persistent (three-stage 192-row ring, compile-time shape).
+void launch_mfma_grouped(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
+                         uint32_t split, bool deep, hipStream_t st) {
+    if (!total_tiles) return;
+    if (deep) {
+        MfmaJob j = one;
+        j.split = split;
+        launch_mfma_jobs(j, jobs_dev, njobs, total_tiles, st);
+        return;
+    }
+    const uint32_t grid = 8 * (uint32_t)std::max(1, cu_count() / 8);
+    auto go = [&](auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        if (jobs_dev)
+            rowsel_mfma_grouped_kernel<false, MODE, RingWide><<<grid, 64 * NWAVE, 0, st>>>(one, jobs_dev, njobs,
+                                                                                        total_tiles);
+        else
+            rowsel_mfma_grouped_kernel<true, MODE, RingWide><<<grid, 64 * NWAVE, 0, st>>>(one, nullptr, 1,
+                                                                                       total_tiles);
+    };
+    switch (split) {
+        case RECOMB_DIRECT: go(std::integral_constant<int, RECOMB_DIRECT>{}); break;
+        case RECOMB_SPLIT: go(std::integral_constant<int, RECOMB_SPLIT>{}); break;
+        default: go(std::integral_constant<int, RECOMB_WIDE>{}); break;
+    }
+    PIR_LAUNCH_CHECK();
+}
+
 // Planes of rows m < 2B only (row stride Mp): rows 2B <= m < Mp are left as
 // they are, since an output row of the GEMM depends on its own query row
 // alone and rows m >= 2B never reach the output.  The k padding up to Kp is
@@ -705,16 +1049,42 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
 // A grouped launch keeps, per distinct set of (DB, batch) items, a plan with
 // the device job table and the scratch of every item (query digit planes and
 // output staging).  The first call for a set allocates it; later calls only
-// enqueue kernels (and may therefore be captured into a hipGraph).
+// enqueue kernels (and may therefore be captured into a hipGraph).  A plan
+// that has been used under stream capture is pinned: a captured graph keeps
+// pointers into its scratch and job table, so it is never evicted to make
+// room for other plans and is released only with one of its DBs.
+//
+// Tile shapes of rowsel_mfma_grouped_kernel (points side by side, waves along
+// m; the waves along n follow): every job of a plan gets its own.
+struct GShape {
+    uint32_t pts, wm;
+    uint32_t wn() const { return NWAVE / (pts * wm); }
+    uint32_t bm() const { return 32 * wm; }
+    uint32_t bn() const { return 32 * wn(); }
+    // fits the three-stage 192-row ring
+    bool deep_ok() const { return pts * (bm() + bn()) == 192; }
+};
+static const GShape G_SHAPES[] = {{1, 4}, {1, 2}, {1, 1}, {1, 8}, {2, 2}, {2, 1}, {2, 4}};
+
+// Output words a shape computes for an mp x d1 point product (padding included).
+static uint64_t shape_work(const GShape &s, uint64_t mp, uint64_t d1) {
+    return (mp + s.bm() - 1) / s.bm() * s.bm() * ((d1 + s.bn() - 1) / s.bn() * s.bn());
+}
+
 struct GroupPlan {
     std::vector<std::pair<const pir_db *, uint32_t>> key;
     int device = 0;
-    uint32_t wm = 4;
+    bool pinned = false;
+    uint32_t forced = 0;            // shape forced by PIR_GROUPED_SHAPE (index + 1), 0 = chosen
+    uint32_t ring_forced = 0;       // PIR_GROUPED_RING: 1 deep, 2 wide, 0 = chosen
     int8_t *scratch = nullptr;
     MfmaJob *jobs_dev = nullptr;
+    // jobs in launch order: 128x64 tiles of the fixed-shape kernel, then its
+    // 64x128 tiles, then the shaped kernel's jobs; launch g covers jobs
+    // [first[g], first[g+1]) with tiles numbered from 0
     std::vector<MfmaJob> jobs;
     std::vector<size_t> item_job;   // item -> job index, or SIZE_MAX for B = 0
-    uint32_t total_tiles = 0;
+    uint32_t first[4] = {0, 0, 0, 0}, tiles[3] = {0, 0, 0}, split = RECOMB_DIRECT;
     ~GroupPlan() {
         if (scratch) {
             int prev = 0;
@@ -728,31 +1098,30 @@ struct GroupPlan {
 };
 
 static std::mutex g_plan_mu;
-static std::list<GroupPlan> g_plans;   // most recently used first
-constexpr size_t MAX_PLANS = 8;
+static std::list<std::shared_ptr<GroupPlan>> g_plans;   // most recently used first
+constexpr size_t MAX_PLANS = 8;                           // unpinned plans kept
 
-// Tile shape that pads fewer rows over the whole group (the choice when
-// timing is switched off with PIR_AUTOTUNE=0).
-static uint32_t pick_group_wm(const pir_rowsel_item *items, uint32_t count) {
-    uint64_t waste4 = 0, waste2 = 0;
-    for (uint32_t i = 0; i < count; ++i) {
-        if (!items[i].B) continue;
-        const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32, d1 = items[i].db->p.d1;
-        const uint64_t m4 = (mp + 127) / 128 * 128, n4 = (d1 + 63) / 64 * 64;
-        const uint64_t m2 = (mp + 63) / 64 * 64, n2 = (d1 + 127) / 128 * 128;
-        const uint64_t w = (uint64_t)items[i].db->mfma.kp * items[i].db->slots();
-        waste4 += (m4 * n4 - mp * d1) * w;
-        waste2 += (m2 * n2 - mp * d1) * w;
+// Drops least recently used unpinned plans beyond MAX_PLANS (lock held).
+static void evict_plans_locked() {
+    size_t unpinned = 0;
+    for (const auto &p : g_plans) unpinned += !p->pinned;
+    for (auto it = g_plans.end(); unpinned > MAX_PLANS && it != g_plans.begin();) {
+        --it;
+        if ((*it)->pinned) continue;
+        it = g_plans.erase(it);
+        --unpinned;
     }
-    return waste4 <= waste2 ? 4u : 2u;
 }
 
-// PIR_MFMA_WM=4 or 2 forces the 128 x 64 or the 64 x 128 tile (0: not forced).
-static uint32_t forced_wm() {
-    if (const char *e = std::getenv("PIR_MFMA_WM")) {
-        const int v = std::atoi(e);
-        if (v == 2 || v == 4) return (uint32_t)v;
-    }
+// PIR_GROUPED_SHAPE="pts,rows,cols" forces one tile shape on every job
+// (returned as index + 1 into G_SHAPES; 0 = not forced or not a shape).
+static uint32_t forced_shape() {
+    const char *e = std::getenv("PIR_GROUPED_SHAPE");
+    if (!e || !*e) return 0;
+    unsigned pts = 0, bm = 0, bn = 0;
+    if (std::sscanf(e, "%u,%u,%u", &pts, &bm, &bn) != 3) return 0;
+    for (uint32_t i = 0; i < sizeof(G_SHAPES) / sizeof(G_SHAPES[0]); ++i)
+        if (G_SHAPES[i].pts == pts && G_SHAPES[i].bm() == bm && G_SHAPES[i].bn() == bn) return i + 1;
     return 0;
 }
 
@@ -768,145 +1137,226 @@ struct EventPair {
     }
 };
 
-static GroupPlan *find_plan(const std::vector<std::pair<const pir_db *, uint32_t>> &key, int dev, uint32_t forced) {
+// PIR_GROUPED_RING=deep|wide restricts the rings (1 deep, 2 wide; 0 = both).
+static uint32_t forced_ring() {
+    const char *e = std::getenv("PIR_GROUPED_RING");
+    if (e && !std::strcmp(e, "deep")) return 1;
+    if (e && !std::strcmp(e, "wide")) return 2;
+    return 0;
+}
+
+static std::shared_ptr<GroupPlan> find_plan(const std::vector<std::pair<const pir_db *, uint32_t>> &key, int dev,
+                                            uint32_t forced, uint32_t ring) {
     for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
-        if (it->key == key && it->device == dev && (!forced || it->wm == forced)) {
+        if ((*it)->key == key && (*it)->device == dev && (*it)->forced == forced && (*it)->ring_forced == ring) {
             g_plans.splice(g_plans.begin(), g_plans, it);
-            return &g_plans.front();
+            return g_plans.front();
         }
     return nullptr;
 }
 
-// Builds the plan of a new item set.  Unless a shape is forced (or timing is
-// off), both tile shapes run once on the call's own inputs, timed with events
-// on the call's stream, and the faster one is kept for every later call.
-static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t count, uint32_t forced,
-                       hipStream_t st) {
-    // layout of the scratch: per job [query digits][staging], then the job table
-    std::vector<size_t> qoff, soff;
+MfmaJob make_shaped_job(const pir_db &db, const int8_t *qd, uint32_t *stage, uint32_t B, uint32_t pts,
+                        uint32_t wm) {
+    const GShape s{pts, wm};
+    MfmaJob j = make_mfma_job(db, qd, stage, B, 0, s.wm);
+    j.pts = s.pts;
+    j.nblk_m = (j.mp + s.bm() - 1) / s.bm();
+    j.nblk_n = (j.d1 + s.bn() - 1) / s.bn();
+    j.tiles = j.groups * j.nblk_m * j.nblk_n;
+    return j;
+}
+
+// A job of a grouped plan in tile shape `s`.
+static MfmaJob grouped_job(const pir_db &db, const int8_t *qd, uint32_t *stage, uint32_t B, const GShape &s) {
+    return make_shaped_job(db, qd, stage, B, s.pts, s.wm);
+}
+
+// Builds the plan of a new item set.  Candidates of a job: the two 192-row
+// shapes in rowsel_mfma_persistent (the "deep" ring: three stages) and the
+// shapes within 25% of the fewest padded output words in the shaped kernel
+// (the "wide" ring).  Without timing (PIR_AUTOTUNE=0) the job takes the
+// candidate with the fewest padded words (the fixed-shape kernel on a tie);
+// otherwise every candidate runs twice, alone, on the job's own inputs (the
+// query digit planes are built first), timed with events on the call's
+// stream, and the fastest is kept for every later call.  The jobs then go to
+// up to three persistent launches (fixed-shape 128x64, fixed-shape 64x128,
+// shaped kernel), all taking the widest recombination form any job needs
+// (each form is exact for the primes of the narrower ones).
+static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
+    // scratch: per job [query digits][staging], then the job tables
+    std::vector<size_t> qoff(count, 0), soff(count, 0);
     size_t bytes = 0;
     for (uint32_t i = 0; i < count; ++i) {
-        if (!items[i].B) {
-            qoff.push_back(0);
-            soff.push_back(0);
-            continue;
-        }
+        if (!items[i].B) continue;
         const pir_db &db = *items[i].db;
         const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32;
-        qoff.push_back(bytes);
+        qoff[i] = bytes;
         bytes += (mfma_query_scratch_bytes(db, items[i].B) + 255) / 256 * 256;
-        soff.push_back(bytes);
+        soff[i] = bytes;
         bytes += ((size_t)db.slots() * mp * staging_stride(db.p.d1) * 4 + 255) / 256 * 256;
     }
     const size_t jobs_off = bytes;
-    bytes += sizeof(MfmaJob) * count + 256;
+    bytes += (sizeof(MfmaJob) * count + 255) / 256 * 256;
     pl.scratch = static_cast<int8_t *>(dev_alloc(bytes));
     pl.jobs_dev = reinterpret_cast<MfmaJob *>(pl.scratch + jobs_off);
 
-    auto set_shape = [&](uint32_t wm) {
-        pl.wm = wm;
-        pl.jobs.clear();
-        pl.item_job.clear();
-        uint32_t tile0 = 0;
-        for (uint32_t i = 0; i < count; ++i) {
-            if (!items[i].B) {
-                pl.item_job.push_back(SIZE_MAX);
-                continue;
-            }
-            pl.item_job.push_back(pl.jobs.size());
-            MfmaJob j = make_mfma_job(*items[i].db, pl.scratch + qoff[i],
-                                      reinterpret_cast<uint32_t *>(pl.scratch + soff[i]), items[i].B, tile0, wm);
-            tile0 += j.tiles;
-            pl.jobs.push_back(j);
+    // candidate (shape, ring) pairs of each job
+    const size_t nshape = sizeof(G_SHAPES) / sizeof(G_SHAPES[0]);
+    const uint32_t ring_forced = pl.ring_forced;
+    struct Cand { uint32_t shape; bool deep; };
+    std::vector<std::vector<Cand>> cands(count);
+    std::vector<size_t> qj;   // item of each job
+    std::vector<MfmaJob> jobs;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!items[i].B) continue;
+        const pir_db &db = *items[i].db;
+        const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32, d1 = db.p.d1;
+        std::vector<uint32_t> order(nshape);
+        for (uint32_t s2 = 0; s2 < nshape; ++s2) order[s2] = s2;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return shape_work(G_SHAPES[a], mp, d1) < shape_work(G_SHAPES[b], mp, d1);
+        });
+        const uint64_t best = shape_work(G_SHAPES[order[0]], mp, d1);
+        std::vector<uint32_t> shapes;
+        if (pl.forced) shapes.push_back(pl.forced - 1);
+        else
+            for (uint32_t s2 : order)
+                if (shape_work(G_SHAPES[s2], mp, d1) * 4 <= best * 5) shapes.push_back(s2);
+        if (!pl.forced && ring_forced != 2)   // the fixed-shape kernel's two shapes, always tried
+            for (uint32_t s2 = 0; s2 < nshape; ++s2)
+                if (G_SHAPES[s2].deep_ok()) cands[i].push_back({s2, true});
+        for (uint32_t s2 : shapes) {
+            if (pl.forced && G_SHAPES[s2].deep_ok() && ring_forced != 2) cands[i].push_back({s2, true});
+            if (ring_forced != 1 || !G_SHAPES[s2].deep_ok()) cands[i].push_back({s2, false});
         }
-        pl.total_tiles = tile0;
-        // one recombination variant per launch: the widest any job needs (each
-        // variant is exact for the primes of the narrower ones)
-        uint32_t split = RECOMB_DIRECT;
-        for (const MfmaJob &j : pl.jobs) split = std::max(split, j.split);
-        for (MfmaJob &j : pl.jobs) j.split = split;
-        if (!pl.jobs.empty()) {
-            PIR_HIP(hipMemcpyAsync(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(),
-                                   hipMemcpyHostToDevice, st));
-            PIR_HIP(hipStreamSynchronize(st));
+        if (!pl.forced) {   // the geometric best first when not timing
+            std::stable_sort(cands[i].begin(), cands[i].end(), [&](const Cand &a, const Cand &b) {
+                return shape_work(G_SHAPES[a.shape], mp, d1) < shape_work(G_SHAPES[b.shape], mp, d1);
+            });
         }
-    };
-
-    uint32_t wm = forced;
-    if (!wm) {
-        const char *tune = std::getenv("PIR_AUTOTUNE");
-        if (tune && std::strcmp(tune, "0") == 0) wm = pick_group_wm(items, count);
+        qj.push_back(i);
+        jobs.push_back(grouped_job(db, pl.scratch + qoff[i], reinterpret_cast<uint32_t *>(pl.scratch + soff[i]),
+                                   items[i].B, G_SHAPES[cands[i][0].shape]));
     }
-    if (!wm) {
-        set_shape(4);
-        if (pl.jobs.empty()) return;
-        // the query digit planes do not depend on the tile shape
-        for (uint32_t i = 0; i < count; ++i)
-            if (pl.item_job[i] != SIZE_MAX)
-                launch_query_digits(*items[i].db, items[i].q_dev, items[i].B,
-                                    const_cast<int8_t *>(pl.jobs[pl.item_job[i]].qd), st);
+    std::vector<uint8_t> deep(jobs.size());
+    for (size_t k = 0; k < jobs.size(); ++k) deep[k] = cands[qj[k]][0].deep;
+    pl.item_job.assign(count, SIZE_MAX);
+    if (jobs.empty()) return;
+    pl.split = RECOMB_DIRECT;
+    for (const MfmaJob &j : jobs) pl.split = std::max(pl.split, j.split);
+
+    const char *tune = std::getenv("PIR_AUTOTUNE");
+    const bool timing = !pl.forced && !(tune && std::strcmp(tune, "0") == 0);
+    if (timing) {
+        for (size_t k = 0; k < jobs.size(); ++k)
+            launch_query_digits(*items[qj[k]].db, items[qj[k]].q_dev, items[qj[k]].B,
+                                const_cast<int8_t *>(jobs[k].qd), st);
         EventPair ev;
-        float best = 0.0f;
-        for (uint32_t cand : {4u, 2u}) {
-            if (cand != pl.wm) set_shape(cand);
-            for (int rep = 0; rep < 2; ++rep) {
-                PIR_HIP(hipEventRecord(ev.a, st));
-                launch_mfma_jobs(pl.jobs[0], pl.jobs_dev, (uint32_t)pl.jobs.size(), pl.total_tiles, st);
-                PIR_HIP(hipEventRecord(ev.b, st));
-                PIR_HIP(hipEventSynchronize(ev.b));
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            const uint32_t i = (uint32_t)qj[k];
+            if (cands[i].size() < 2) continue;
+            float best = 0.0f;
+            bool first = true;
+            for (const Cand &c : cands[i]) {
+                MfmaJob probe = grouped_job(*items[i].db, jobs[k].qd, jobs[k].out, items[i].B, G_SHAPES[c.shape]);
+                probe.split = pl.split;
                 float ms = 0.0f;
-                PIR_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-                if (!wm || ms < best) {
+                for (int rep = 0; rep < 2; ++rep) {
+                    PIR_HIP(hipEventRecord(ev.a, st));
+                    launch_mfma_grouped(probe, nullptr, 1, probe.tiles, pl.split, c.deep, st);
+                    PIR_HIP(hipEventRecord(ev.b, st));
+                    PIR_HIP(hipEventSynchronize(ev.b));
+                    float t = 0.0f;
+                    PIR_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+                    ms = rep ? std::min(ms, t) : t;
+                }
+                if (first || ms < best) {
                     best = ms;
-                    wm = cand;
+                    jobs[k] = probe;
+                    deep[k] = c.deep;
+                    first = false;
                 }
             }
         }
     }
-    if (wm != pl.wm || pl.jobs.empty()) set_shape(wm);
+    // launch order: fixed-shape 128x64, fixed-shape 64x128, shaped kernel;
+    // tile numbers restart at 0 in each launch
+    for (int g = 0; g < 3; ++g) {
+        pl.first[g] = (uint32_t)pl.jobs.size();
+        uint32_t tile0 = 0;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            const int gk = !deep[k] ? 2 : jobs[k].wm == 4 ? 0 : 1;
+            if (gk != g) continue;
+            MfmaJob j = jobs[k];
+            j.tile0 = tile0;
+            j.split = pl.split;
+            tile0 += j.tiles;
+            pl.item_job[qj[k]] = pl.jobs.size();
+            pl.jobs.push_back(j);
+        }
+        pl.tiles[g] = tile0;
+    }
+    pl.first[3] = (uint32_t)pl.jobs.size();
+    PIR_HIP(hipMemcpyAsync(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(), hipMemcpyHostToDevice, st));
+    PIR_HIP(hipStreamSynchronize(st));
 }
 
-static GroupPlan &get_plan(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
+// The plan of an item list (built on first use).  The caller holds a
+// reference, so a concurrent eviction cannot free it while it is in use.
+static std::shared_ptr<GroupPlan> get_plan(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
     std::vector<std::pair<const pir_db *, uint32_t>> key(count);
     for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
-    const uint32_t forced = forced_wm();
+    const uint32_t forced = forced_shape(), ring = forced_ring();
     int dev = 0;
     PIR_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(g_plan_mu);
-    if (GroupPlan *pl = find_plan(key, dev, forced)) return *pl;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     PIR_HIP(hipStreamIsCapturing(st, &cap));
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    if (auto pl = find_plan(key, dev, forced, ring)) {
+        if (cap != hipStreamCaptureStatusNone) pl->pinned = true;
+        return pl;
+    }
     PIR_REQUIRE(cap == hipStreamCaptureStatusNone,
                 "pir_rowsel_grouped: the first call for a set of item shapes allocates and cannot be captured");
-    g_plans.emplace_front();
-    GroupPlan &pl = g_plans.front();
-    pl.key = key;
-    pl.device = dev;
-    try {
-        build_plan(pl, items, count, forced, st);
-    } catch (...) {
-        g_plans.pop_front();   // frees what was allocated
-        throw;
-    }
-    while (g_plans.size() > MAX_PLANS) g_plans.pop_back();
-    return g_plans.front();
+    auto pl = std::make_shared<GroupPlan>();
+    pl->key = key;
+    pl->device = dev;
+    pl->forced = forced;
+    pl->ring_forced = ring;
+    build_plan(*pl, items, count, st);   // on failure the plan frees what it allocated
+    g_plans.push_front(pl);
+    evict_plans_locked();
+    return pl;
 }
 
-bool group_plan_tile(const pir_rowsel_item *items, uint32_t count, uint32_t *bm, uint32_t *bn) {
+bool group_plan_tiles(const pir_rowsel_item *items, uint32_t count, uint32_t *tiles) {
     std::vector<std::pair<const pir_db *, uint32_t>> key(count);
     for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
     int dev = 0;
     PIR_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    GroupPlan *pl = find_plan(key, dev, 0);
+    std::shared_ptr<GroupPlan> pl;
+    for (const auto &p : g_plans)
+        if (p->key == key && p->device == dev) {
+            pl = p;
+            break;
+        }
     if (!pl) return false;
-    *bm = 32 * pl->wm;
-    *bn = 32 * (NWAVE / pl->wm);
+    for (uint32_t i = 0; i < count; ++i) {
+        uint32_t *t = tiles + 3 * i;
+        t[0] = t[1] = t[2] = 0;
+        if (pl->item_job[i] == SIZE_MAX) continue;
+        const MfmaJob &j = pl->jobs[pl->item_job[i]];
+        t[0] = j.pts;
+        t[1] = 32 * j.wm;
+        t[2] = 32 * (NWAVE / (j.pts * j.wm));
+    }
     return true;
 }
 
 void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
-    GroupPlan &pl = get_plan(items, count, st);
+    const std::shared_ptr<GroupPlan> plan = get_plan(items, count, st);
+    GroupPlan &pl = *plan;
     if (pl.jobs.empty()) return;
     for (uint32_t i = 0; i < count; ++i)
         if (pl.item_job[i] != SIZE_MAX)
@@ -914,7 +1364,10 @@ void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hi
                                 const_cast<int8_t *>(pl.jobs[pl.item_job[i]].qd), st);
     {
         KernelTimer::Scope timed(st);
-        launch_mfma_jobs(pl.jobs[0], pl.jobs_dev, (uint32_t)pl.jobs.size(), pl.total_tiles, st);
+        for (int g = 0; g < 3; ++g)
+            if (pl.first[g + 1] > pl.first[g])
+                launch_mfma_grouped(pl.jobs[pl.first[g]], pl.jobs_dev + pl.first[g], pl.first[g + 1] - pl.first[g],
+                                    pl.tiles[g], pl.split, g < 2, st);
     }
     for (uint32_t i = 0; i < count; ++i) {
         if (pl.item_job[i] == SIZE_MAX) continue;
@@ -923,9 +1376,13 @@ void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hi
     }
 }
 
-void release_group_plans() {
+void release_group_plans(const pir_db *db) {
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    g_plans.clear();
+    g_plans.remove_if([db](const std::shared_ptr<GroupPlan> &p) {
+        for (const auto &k : p->key)
+            if (k.first == db) return true;
+        return false;
+    });
 }
 
 }  // namespace pir

@@ -14,6 +14,7 @@
 // away, so later steps cannot write to it) -> FREE (last step retired).
 #include <chrono>
 #include <deque>
+#include <unordered_set>
 #include <vector>
 
 #include "common.h"
@@ -111,7 +112,7 @@ struct pir_server {
     const pir_db *db = nullptr;
     int device = 0;
     hipStream_t st = nullptr;
-    uint32_t capacity = 0, chunks = 0, pipeline = 2, cg = 0, gall = 0, mstride = 0;
+    uint32_t capacity = 0, chunks = 0, pipeline = 2, cg = 0, gall = 0, mstride = 0, max_waiting = 0;
     uint64_t device_bytes = 0;
     int8_t *qd = nullptr;
     uint32_t *stage = nullptr;
@@ -121,6 +122,7 @@ struct pir_server {
     std::deque<Pending> waitq;
     std::deque<Step> inflight;
     std::deque<pir_completion> done;
+    std::unordered_set<uint64_t> live_ids;   // ids submitted whose completion is not yet returned
     std::vector<hipEvent_t> spare_events;
     uint64_t next_chunk = 0, steps = 0, admitted = 0, completed = 0;
 
@@ -214,12 +216,28 @@ struct pir_server {
         const uint32_t rows = 2 * (hi + 1);
         const uint32_t c = (uint32_t)(next_chunk++ % chunks);
         const uint32_t g_begin = c * cg, ng = std::min(cg, gall - g_begin);
-        MfmaJob job = make_mfma_job(*db, qd, stage, hi + 1, 0, pick_wm(hi + 1));
+        // the tile shape that pads the fewest output words for this many rows
+        // (32 x 256 while at most 16 clients are active: all eight waves on
+        // useful sub-tiles, 256 DB columns per pipeline stage)
+        const uint32_t mp = (rows + 31) / 32 * 32;
+        uint32_t pts = 1, wm = 2;
+        uint64_t best = UINT64_MAX;
+        for (const auto &sh : {std::pair<uint32_t, uint32_t>{1, 4}, {1, 2}, {1, 1}, {1, 8}, {2, 2}, {2, 1}, {2, 4}}) {
+            const uint64_t bm = 32 * sh.second, bn = 32 * (8 / (sh.first * sh.second));
+            const uint64_t w = (mp + bm - 1) / bm * bm * ((db->p.d1 + bn - 1) / bn * bn);
+            if (w < best) {
+                best = w;
+                pts = sh.first;
+                wm = sh.second;
+            }
+        }
+        MfmaJob job = make_shaped_job(*db, qd, stage, hi + 1, pts, wm);
         job.mstride = mstride;
         job.g_begin = g_begin;
         job.groups = ng;
         job.tiles = ng * job.nblk_m * job.nblk_n;
-        launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
+        const bool deep = pts == 1 && (wm == 2 || wm == 4);   // the 192-row shapes take the three-stage ring
+        launch_mfma_grouped(job, nullptr, 1, job.tiles, job.split, deep, st);
         const uint32_t cp = 4 * ng, nblk_n = (db->p.d1 + 63) / 64, nblk_p = (cp + 63) / 64;
         const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_p;
         PIR_REQUIRE(blocks < (1ull << 31), "scatter launch too large");
@@ -271,6 +289,7 @@ pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_
             srv->db = db;
             srv->device = db->device;
             srv->pipeline = o.pipeline ? o.pipeline : 2;
+            srv->max_waiting = o.max_waiting;
             srv->gall = (uint32_t)(db->slots() / 4);
             uint32_t chunks = o.chunks ? o.chunks : 16;
             PIR_REQUIRE(chunks <= srv->gall, "chunks must be <= L*N/4 = %u", srv->gall);
@@ -319,12 +338,29 @@ pir_status pir_serve_step(pir_server *srv, const pir_request *arrivals, uint32_t
         const double t = now_s();
         const auto &p = srv->db->p;
         const size_t qb = (size_t)2 * p.d0 * srv->db->slots() * 4, ob = (size_t)2 * p.d1 * srv->db->slots() * 4;
+        {
+            // ids must be unique among live requests: checked before anything is queued
+            std::unordered_set<uint64_t> fresh;
+            for (uint32_t i = 0; i < n_arrivals; ++i)
+                PIR_REQUIRE(!srv->live_ids.count(arrivals[i].id) && fresh.insert(arrivals[i].id).second,
+                            "request id %llu is already live", (unsigned long long)arrivals[i].id);
+        }
         for (uint32_t i = 0; i < n_arrivals; ++i) {
             const pir_request &r = arrivals[i];
+            srv->live_ids.insert(r.id);   // every arrival gets exactly one completion
             const auto qa = reinterpret_cast<uintptr_t>(r.q_dev), oa = reinterpret_cast<uintptr_t>(r.out_dev);
             const bool bad = !r.q_dev || !r.out_dev || qa % 16 || oa % 16 || (qa < oa + ob && oa < qa + qb);
-            if (bad) srv->done.push_back(pir_completion{r.id, PIR_EINVAL, 0, t, t, t});
-            else srv->waitq.push_back({r, t});
+            if (bad) {
+                srv->done.push_back(pir_completion{r.id, PIR_EINVAL, 0, t, t, t});
+                continue;
+            }
+            if (srv->max_waiting && srv->waitq.size() >= srv->max_waiting) {
+                srv->done.push_back(pir_completion{r.id, PIR_EBUSY, 0, t, t, t});
+                continue;
+            }
+            // the query's producer: later reads on the server stream wait for it
+            if (r.ready_event) PIR_HIP(hipStreamWaitEvent(srv->st, reinterpret_cast<hipEvent_t>(r.ready_event), 0));
+            srv->waitq.push_back({r, t});
         }
         srv->retire();
         while (srv->inflight.size() < srv->pipeline) {
@@ -334,6 +370,7 @@ pir_status pir_serve_step(pir_server *srv, const pir_request *arrivals, uint32_t
         uint32_t k = 0;
         while (k < cap && !srv->done.empty()) {
             done[k++] = srv->done.front();
+            srv->live_ids.erase(srv->done.front().id);
             srv->done.pop_front();
         }
         if (n_done) *n_done = k;

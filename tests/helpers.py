@@ -85,3 +85,26 @@ def host_query(seed, B, d0, primes, n, sub=0):
     with ThreadPoolExecutor(_workers()) as ex:
         list(ex.map(fill, range(B)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# guard bands: an output view with canary words on both sides, to show that a
+# kernel writes inside its output and nowhere next to it
+GUARD_WORDS = 256                      # 1 KiB each side (keeps 16-byte alignment)
+CANARY = 0x5EC0DE42
+
+
+def guarded_u32(count):
+    """(buffer, view): `view` is `count` words in the middle of `buffer`,
+    which has GUARD_WORDS canary words before and after it."""
+    import torch
+    buf = torch.full((int(count) + 2 * GUARD_WORDS,), CANARY, dtype=torch.int32, device="cuda")
+    return buf, buf[GUARD_WORDS: GUARD_WORDS + int(count)]
+
+
+def assert_guards(buf):
+    import torch
+    canary = torch.tensor(CANARY, dtype=torch.int32, device=buf.device)
+    head, tail = buf[:GUARD_WORDS], buf[-GUARD_WORDS:]
+    assert bool(torch.all(head == canary)) and bool(torch.all(tail == canary)), \
+        "a kernel wrote into the guard band around its output"

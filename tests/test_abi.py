@@ -13,7 +13,7 @@ import paper_2604_04696_amd as pir
 import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("pir.h", "pir_synth.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pir.h", "pir_synth.h", "pir_peak.h")]
 
 
 def declared_functions():
@@ -112,9 +112,9 @@ def test_null_arguments(L):
     assert L.pir_db_load_ntt(None, None, 0, 1, 0, None) == pir.PIR_EINVAL
     assert L.pir_db_create(None, 1, None) == pir.PIR_EINVAL
     L.pir_db_free(None)   # no-op
-    tm, tn = ctypes.c_uint32(), ctypes.c_uint32()
-    assert L.pir_rowsel_grouped_tile(None, 0, None, None) == pir.PIR_EINVAL
-    assert L.pir_rowsel_grouped_tile(None, 1, ctypes.byref(tm), ctypes.byref(tn)) == pir.PIR_EINVAL
+    tiles = (ctypes.c_uint32 * 3)()
+    assert L.pir_rowsel_grouped_tiles(None, 0, None) == pir.PIR_EINVAL
+    assert L.pir_rowsel_grouped_tiles(None, 1, tiles) == pir.PIR_EINVAL
     assert "NULL" in pir.pir_last_error()
 
 
@@ -180,3 +180,15 @@ def test_library_load_brings_torch_first():
             "assert 'torch' in sys.modules\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
+
+
+def test_peak_argument_checks(L):
+    d = ctypes.c_double()
+    assert L.pir_peak_mfma_i8(1, 0, None, ctypes.byref(d), None) == pir.PIR_EINVAL
+    assert L.pir_peak_mfma_i8(0, 0, ctypes.byref(d), ctypes.byref(d), None) == pir.PIR_EINVAL
+    assert "iters" in pir.pir_last_error()
+    assert L.pir_peak_valu_mad64(1 << 25, ctypes.byref(d), ctypes.byref(d), None) == pir.PIR_EINVAL
+    assert L.pir_peak_hbm_read(None, 16, ctypes.byref(d), None) == pir.PIR_EINVAL
+    assert L.pir_peak_hbm_read(ctypes.c_void_p(4096), 10, ctypes.byref(d), None) == pir.PIR_EINVAL
+    assert "multiple of 16" in pir.pir_last_error()
+

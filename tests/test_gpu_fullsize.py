@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import device_db, device_query, empty_u32, host_db_ntt, host_query, np_u32, to_dev
+from helpers import assert_guards, device_db, device_query, guarded_u32, host_db_ntt, host_query, np_u32, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 torch = pytest.importorskip("torch")
@@ -65,10 +65,10 @@ def batched_want(dhat):
 
 
 def _run(pir, db, q, B, path, w, fn=None):
-    out = empty_u32(B * 2 * w.d1 * w.slots)
-    out.fill_(-1)
+    guard, out = guarded_u32(B * 2 * w.d1 * w.slots)
     (fn or pir.pir_rowsel)(db, q, out, path)
     torch.cuda.synchronize()
+    assert_guards(guard)
     return np_u32(out).reshape(B, 2, w.d1, w.nprimes, w.n)
 
 

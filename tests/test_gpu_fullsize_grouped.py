@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import device_db, device_query, empty_u32, host_db_ntt, host_query, np_u32
+from helpers import assert_guards, device_db, device_query, empty_u32, guarded_u32, host_db_ntt, host_query, np_u32
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 torch = pytest.importorskip("torch")
@@ -39,18 +39,20 @@ def pir():
 
 @pytest.fixture(scope="module")
 def grouped(pir):
-    items, outs = [], []
+    items, outs, guards = [], [], []
     for it in INSTS:
         log(f"device: instance {it.index} D0={it.d0} D1={it.d1} B={it.clients}")
         db = device_db(pir, it.n, it.primes, it.d0, it.d1, it.seed, pir.PIR_LAYOUT_MFMA, sub=it.index)
         q = device_query(pir, it.clients, it.d0, it.primes, it.n, it.seed, sub=it.index)
-        out = empty_u32(it.clients * 2 * it.d1 * 2 * it.n)
-        out.fill_(-1)
+        guard, out = guarded_u32(it.clients * 2 * it.d1 * 2 * it.n)
         items.append((db, q, it.clients, out))
         outs.append(out)
+        guards.append(guard)
     log("grouped call (eager; builds the plan)")
     pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
     torch.cuda.synchronize()
+    for g in guards:
+        assert_guards(g)
 
     # capture the same call into a graph writing to other buffers, replay it
     # twice with eager work in between, compare each replay with eager

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import device_db, device_query, empty_u32, np_u32, to_dev
+from helpers import assert_guards, empty_u32, guarded_u32, np_u32, to_dev
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -80,27 +80,75 @@ def test_grouped_graph_replay(pir):
                 assert np.array_equal(got, want), f"replay {rep} differs"
 
 
+SHAPES = [(1, 128, 64), (1, 64, 128), (1, 32, 256), (1, 256, 32), (2, 64, 64), (2, 32, 128), (2, 128, 32)]
+
+
 def test_grouped_tile_choice(pir, monkeypatch):
-    """The plan keeps a tile shape, timed or forced, and any shape gives the
-    same bits."""
+    """Every item of a plan gets a tile shape, timed, geometric or forced, and
+    every shape gives the oracle's bits."""
     items, wants = _small_items(pir)
     with pytest.raises(pir.PirError, match="no grouped plan"):
-        pir.pir_rowsel_grouped_tile(items[:3])
-    outs = {}
-    for forced in ("", "4", "2"):
-        monkeypatch.setenv("PIR_MFMA_WM", forced)
+        pir.pir_rowsel_grouped_tiles(items)
+    settings = [("", "")] + [("", "0")] + [(",".join(map(str, s)), "") for s in SHAPES]
+    for forced, tune in settings:
+        monkeypatch.setenv("PIR_GROUPED_SHAPE", forced)
+        monkeypatch.setenv("PIR_AUTOTUNE", tune)
         for _, _, B, out in items:
-            out.fill_(0)
-        pir.pir_rowsel_grouped(items[:3], pir.PIR_PATH_MFMA_I8)
+            out.fill_(-1)
+        pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
         torch.cuda.synchronize()
-        tm, tn = pir.pir_rowsel_grouped_tile(items[:3])
-        assert (tm, tn) in ((128, 64), (64, 128))
-        if forced:
-            assert tm == 32 * int(forced)
-        for (db, q, B, out), want in zip(items[:3], wants[:3]):
-            if B:
-                assert np.array_equal(np_u32(out)[: want.size].reshape(want.shape), want), forced
-    monkeypatch.delenv("PIR_MFMA_WM")
+        tiles = pir.pir_rowsel_grouped_tiles(items)
+        for (db, q, B, out), want, t in zip(items, wants, tiles):
+            if not B:
+                assert t == (0, 0, 0) and np.all(np_u32(out) == 0xFFFFFFFF)
+                continue
+            assert t in SHAPES
+            if forced:
+                assert ",".join(map(str, t)) == forced
+            assert np.array_equal(np_u32(out)[: want.size].reshape(want.shape), want), (forced, tune, t)
+    monkeypatch.delenv("PIR_GROUPED_SHAPE")
+    monkeypatch.delenv("PIR_AUTOTUNE")
+
+
+RINGS = [(s, "wide") for s in SHAPES] + [(s, "deep") for s in SHAPES if s[0] * (s[1] + s[2]) == 192]
+
+
+@pytest.mark.parametrize("shape,ring", RINGS, ids=["x".join(map(str, s)) + "-" + r for s, r in RINGS])
+def test_grouped_shape_long_k_and_extremes(pir, monkeypatch, shape, ring):
+    """Each tile shape, in each pipeline ring it fits, on a K of 2100 rows
+    (two int32 accumulation chunks), all-(q-1) residues (every output equals
+    D0 mod q, since (q-1)^2 = 1) and uniform residues, ragged D1 and batch."""
+    monkeypatch.setenv("PIR_GROUPED_SHAPE", ",".join(map(str, shape)))
+    monkeypatch.setenv("PIR_GROUPED_RING", ring)
+    primes = synth.PRIMES_N4096
+    n, d0 = 16, 2100
+    cases = [(d0, 37, 5, "ones"), (d0, 70, 19, "uniform"), (100, 200, 3, "uniform")]
+    items, wants, guards = [], [], []
+    for i, (k, d1, B, kind) in enumerate(cases):
+        if kind == "ones":
+            dhat = np.broadcast_to(np.array(primes, np.uint32)[None, None, :, None] - 1, (k, d1, 2, n)).copy()
+            query = np.broadcast_to(np.array(primes, np.uint32)[None, None, None, :, None] - 1,
+                                    (B, 2, k, 2, n)).copy()
+        else:
+            dhat = oracle.ntt_db(synth.db_coeffs(40 + i, k, d1, 2, n), primes)
+            query = synth.query_uniform(50 + i, B, k, primes, n)
+        db = pir.pir_db_create(pir.make_params(n, primes, k, d1), pir.PIR_LAYOUT_MFMA)
+        pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+        guard, out = guarded_u32(B * 2 * d1 * 2 * n)
+        guards.append(guard)
+        items.append((db, to_dev(query), B, out))
+        want = oracle.rowsel(query, dhat, primes)
+        if kind == "ones":
+            assert np.all(want == np.array([k % q for q in primes], np.uint32)[None, None, None, :, None])
+        wants.append(want)
+    pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    assert all(t == shape for t in pir.pir_rowsel_grouped_tiles(items))
+    for (db, q, B, out), want, guard in zip(items, wants, guards):
+        assert np.array_equal(np_u32(out).reshape(want.shape), want), (shape, ring)
+        assert_guards(guard)
+    monkeypatch.delenv("PIR_GROUPED_SHAPE")
+    monkeypatch.delenv("PIR_GROUPED_RING")
 
 
 def test_grouped_first_call_refuses_capture(pir):
@@ -121,33 +169,40 @@ def test_grouped_rejects_overlapping_outputs(pir):
         pir.pir_rowsel_grouped([(db, q, B, out), (db, q, B, out)])
 
 
-def test_grouped_full_size_sampled(pir):
-    """The 24 uneven instances (N = 4096, two primes) in one call; each
-    instance is checked against the oracle on two sampled columns of its
-    first and last client, and the whole call equals separate calls."""
-    insts = synth.grouped_instances()
-    items = []
-    for it in insts:
-        print("building instance", it.index, it.d0, it.d1, it.clients, flush=True)
-        db = device_db(pir, it.n, it.primes, it.d0, it.d1, it.seed, pir.PIR_LAYOUT_MFMA, sub=it.index)
-        q = device_query(pir, it.clients, it.d0, it.primes, it.n, it.seed, sub=it.index)
-        out = empty_u32(it.clients * 2 * it.d1 * 2 * it.n)
-        items.append((db, q, it.clients, out))
-    print("grouped call", flush=True)
+def test_grouped_graph_survives_other_plans_and_frees(pir):
+    """A plan used under capture stays alive: freeing an unrelated DB and
+    building more than the cache's worth of other plans leaves the graph's
+    replays equal to the oracle."""
+    items, wants = _small_items(pir)
+    items, wants = items[:3], wants[:3]
     pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
     torch.cuda.synchronize()
-    for it, (db, q, B, out) in zip(insts, items):
-        sep = empty_u32(out.numel())
-        pir.pir_rowsel(db, q, sep, pir.PIR_PATH_MFMA_I8)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    # an unrelated DB created and freed
+    other = pir.pir_db_create(pir.make_params(16, synth.PRIMES_N4096, 8, 8))
+    pir.pir_db_free(other)
+    # ten other plans (one-item lists of distinct batch sizes) evict every
+    # unpinned plan
+    db0 = items[0][0]
+    extra = empty_u32(10 * 2 * db0.d1 * 2 * db0.n)
+    qz = to_dev(np.zeros((10, 2, db0.d0, 2, db0.n), np.uint32))
+    for b in range(1, 11):
+        pir.pir_rowsel_grouped([(db0, qz[: b * 2 * db0.d0 * 2 * db0.n], b, extra[: b * 2 * db0.d1 * 2 * db0.n])],
+                               pir.PIR_PATH_MFMA_I8)
+    assert np.all(np_u32(extra) == 0)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for _, _, B, out in items:
+            out.fill_(0)
         torch.cuda.synchronize()
-        assert torch.equal(sep, out), f"instance {it.index}: grouped != separate"
-        cols = [0, it.d1 - 1]
-        clients = sorted({0, B - 1})
-        coeffs = synth.db_coeffs(it.seed, it.d0, it.d1, 2, it.n, sub=it.index, cols=cols)
-        qv = synth.query_uniform(it.seed, B, it.d0, it.primes, it.n, sub=it.index, clients=clients)
-        want = oracle.rowsel(qv, oracle.ntt_db(coeffs, it.primes), it.primes)
-        got = np_u32(out).reshape(B, 2, it.d1, 2, it.n)[clients][:, :, cols]
-        assert np.array_equal(got, want), f"instance {it.index} differs from the oracle"
-        del sep
-    for db, q, B, out in items:
-        pir.pir_db_free(db)
+        g.replay()
+        torch.cuda.synchronize()
+        for (db, q, B, out), want in zip(items, wants):
+            if B:
+                got = np_u32(out)[: want.size].reshape(want.shape)
+                assert np.array_equal(got, want), f"replay {rep} differs"

@@ -6,7 +6,7 @@ import pytest
 import oracle
 import oracle.rlwe as rlwe
 import synth
-from helpers import device_db, device_query, empty_u32, np_u32, to_dev
+from helpers import assert_guards, device_db, device_query, empty_u32, guarded_u32, np_u32, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -116,12 +116,12 @@ def test_rowsel_matches_oracle(pir, shape, path):
     want = oracle.rowsel(query, oracle.ntt_db(coeffs, primes), primes)
     db = pir.pir_db_create(pir.make_params(n, primes, d0, d1))
     pir.pir_db_load_ntt(db, to_dev(coeffs), domain=pir.PIR_DOMAIN_COEFF)
-    out = empty_u32(want.size)
-    out.fill_(-1)
+    guard, out = guarded_u32(want.size)
     pir.pir_rowsel(db, to_dev(query), out, path)
     torch.cuda.synchronize()
     got = np_u32(out).reshape(want.shape)
     assert np.array_equal(got, want), f"{(got != want).sum()} of {want.size} words differ"
+    assert_guards(guard)
 
 
 @BOTH

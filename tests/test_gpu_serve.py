@@ -154,3 +154,62 @@ def test_serve_full_size_sampled(pir):
         out = np_u32(outs[i]).reshape(1, 2, w.d1, 2, w.n)[:, :, cols]
         assert np.array_equal(out, want), f"request {i}"
     pir.pir_db_free(db)
+
+
+def test_serve_duplicate_ids_rejected(pir, served):
+    db, queries, wants = served
+    srv = pir.pir_server_create(db, max_clients=2, chunks=2)
+    q, out, out2 = to_dev(queries[0]), empty_u32(2 * D1 * 2 * N), empty_u32(2 * D1 * 2 * N)
+    with pytest.raises(ValueError, match="already live"):
+        pir.pir_serve_step(srv, [(5, q, out), (5, q, out2)])
+    # the C call itself refuses a live id and queues nothing
+    import ctypes
+    arr = (pir.pir_request * 2)()
+    for i, o in enumerate((out, out2)):
+        arr[i].id, arr[i].q_dev, arr[i].out_dev, arr[i].ready_event = 9, q.data_ptr(), o.data_ptr(), None
+    nd = ctypes.c_uint32()
+    st = pir.lib().pir_serve_step(srv.handle, ctypes.cast(arr, ctypes.c_void_p), 2, None, 0, ctypes.byref(nd))
+    assert st == pir.PIR_EINVAL and "already live" in pir.pir_last_error()
+    assert pir.pir_server_get_stats(srv).waiting == 0 and pir.pir_server_get_stats(srv).admitted == 0
+    got = run_until(pir, srv, {0: [(5, q, out)]}, 1)
+    with pytest.raises(ValueError, match="already live"):
+        pir.pir_serve_step(srv, [(6, q, out2), (6, q, out2)])
+    torch.cuda.synchronize()
+    assert got[5].status == 0
+    assert np.array_equal(np_u32(out).reshape(wants[0].shape), wants[0])
+    pir.pir_server_destroy(srv)
+
+
+def test_serve_max_waiting_busy(pir, served):
+    """With one slot and room for two waiting requests, a burst of five
+    admits one, queues two and completes two at once with PIR_EBUSY."""
+    db, queries, wants = served
+    srv = pir.pir_server_create(db, max_clients=1, chunks=2, max_waiting=2)
+    outs = [empty_u32(2 * D1 * 2 * N) for _ in range(5)]
+    burst = [(i, to_dev(queries[i]), outs[i]) for i in range(5)]
+    got = run_until(pir, srv, {0: burst}, 5)
+    torch.cuda.synchronize()
+    busy = sorted(i for i in range(5) if got[i].status == pir.PIR_EBUSY)
+    ok = sorted(i for i in range(5) if got[i].status == 0)
+    assert busy == [2, 3, 4] and ok == [0, 1]
+    for i in ok:
+        assert np.array_equal(np_u32(outs[i]).reshape(wants[i].shape), wants[i]), f"request {i}"
+    pir.pir_server_destroy(srv)
+
+
+def test_serve_reads_query_after_its_producer(pir, served):
+    """The query is written by work still queued on torch's stream (a copy
+    behind a GPU sleep) when it is submitted: the server waits for it."""
+    db, queries, wants = served
+    srv = pir.pir_server_create(db, max_clients=2, chunks=2)
+    src = to_dev(queries[3])
+    qbuf = torch.zeros_like(src)
+    out = empty_u32(2 * D1 * 2 * N)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(200_000_000)          # ~0.1 s of device time before the copy
+    qbuf.copy_(src)
+    got = run_until(pir, srv, {0: [(3, qbuf, out)]}, 1)
+    torch.cuda.synchronize()
+    assert got[3].status == 0
+    assert np.array_equal(np_u32(out).reshape(wants[3].shape), wants[3])
+    pir.pir_server_destroy(srv)
