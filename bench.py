@@ -156,10 +156,11 @@ def grouped_section(pir, reps: int):
     return res
 
 
-def serving_section(pir, n_requests: int, loads):
+def serving_section(pir, n_requests: int, rates):
     """pir_serve_step over the 1024 x 1024 DB: saturated throughput with the
-    admission cap full, then seeded Poisson streams at each of `loads` x
-    that rate."""
+    admission cap full, then seeded Poisson streams at each of the frozen
+    `rates` (queries/s; 0.7x and 0.9x the saturated rate as calibrated once,
+    synth.SERVE_RATES_QPS)."""
     import numpy as np
     import torch
     import synth
@@ -194,8 +195,7 @@ def serving_section(pir, n_requests: int, loads):
     qps_sat = sat_n / dt
     runs = []
     same = True
-    for load in loads:
-        lam = load * qps_sat
+    for lam in rates:
         arr = synth.poisson_arrivals(w.seed, lam, n_requests)
         choice = synth.pool_choice(w.seed, n_requests)
         got, t0, dt, active = drive(arr, choice)
@@ -203,7 +203,8 @@ def serving_section(pir, n_requests: int, loads):
         lat = np.array([c.t_done - (t0 + arr[c.id]) for c in got])
         edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 4097]
         hist = np.histogram(np.array(active), bins=edges)[0]
-        runs.append({"load": load, "offered_qps": round(lam, 1), "requests": n_requests,
+        runs.append({"offered_qps": round(lam, 1), "load_vs_this_run_saturated": round(lam / qps_sat, 3),
+                     "requests": n_requests,
                      "qps": round(n_requests / dt, 1),
                      "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
@@ -220,6 +221,7 @@ def serving_section(pir, n_requests: int, loads):
     pir.pir_server_destroy(srv)
     pir.pir_db_free(db)
     return {"workload": w.name, "capacity": cap, "chunks": chunks, "saturated_qps": round(qps_sat, 1),
+            "frozen_rates_qps": list(rates), "frozen_from_saturated_qps": synth.SERVE_SATURATED_QPS,
             "runs": runs, "in_mix_equals_alone": same, "steps": st.steps}
 
 
@@ -460,8 +462,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving figures")
     ap.add_argument("--no-coltor", action="store_true", help="skip the ColTor-stage figures")
     ap.add_argument("--serve-requests", type=int, default=1024)
-    ap.add_argument("--serve-loads", default="0.7,0.9",
-                    help="offered loads as fractions of the saturated rate")
+    ap.add_argument("--serve-rates", default=None,
+                    help="offered Poisson rates in queries/s (default: the frozen 0.7x and 0.9x of the "
+                         "calibrated saturated rate, synth.SERVE_RATES_QPS)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calib", action="store_true",
@@ -625,7 +628,8 @@ def main():
     if not args.no_serve:
         log("serving")
         line["serving"] = serving_section(pir, args.serve_requests,
-                                          [float(x) for x in args.serve_loads.split(",")])
+                                          [float(x) for x in args.serve_rates.split(",")] if args.serve_rates
+                                          else list(synth.SERVE_RATES_QPS))
         torch.cuda.empty_cache()
         log(f"serving: {line['serving']}")
 

@@ -356,8 +356,9 @@ pir_status pir_ntt_inverse(const uint32_t *in_dev, uint32_t *out_dev, uint32_t c
  * every pir_rowsel and pir_rowsel_grouped call records two HIP events on
  * its stream around its main kernel: the streaming kernel (VALU path,
  * B <= 4), the tiled kernel (VALU path, B > 4) or the persistent INT8 GEMM
- * (MFMA path); with 32-bit primes the streaming kernel runs once per client,
- * each launch timed.  Query ingest, output transposes and scratch allocation
+ * (MFMA path; the up to three GEMM launches of a grouped call count as one);
+ * with 32-bit primes the streaming kernel runs once per client, each launch
+ * timed.  Every serving step's GEMM is timed the same way.  Query ingest, output transposes and scratch allocation
  * fall outside the events.  pir_kernel_time_read waits for every recorded
  * event, stores how many launches were timed and their summed duration in
  * milliseconds, and forgets them (PIR_EINVAL if an out pointer is NULL).

@@ -48,6 +48,9 @@ void launch_mfma_jobs(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njob
 // shapes), else the two-stage 320-row ring (every shape).
 void launch_mfma_grouped(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t njobs, uint32_t total_tiles,
                          uint32_t split, bool deep, hipStream_t st);
+// Tile shape for one job of mp rows and d1 columns (serving steps); deep: run
+// it through launch_mfma_grouped's fixed-shape kernel.
+void pick_shape(uint32_t mp, uint32_t d1, uint32_t *pts, uint32_t *wm, bool *deep);
 // A job for that kernel in tile shape pts x 32wm x 32wn (pts * wm * wn = 8).
 MfmaJob make_shaped_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t B, uint32_t pts, uint32_t wm);
 // Staging row stride of a DB with d1 columns (16-byte aligned rows).

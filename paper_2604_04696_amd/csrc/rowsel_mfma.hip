@@ -1113,6 +1113,14 @@ static void evict_plans_locked() {
     }
 }
 
+// PIR_GROUPED_RING=deep|wide restricts the rings (1 deep, 2 wide; 0 = both).
+static uint32_t forced_ring() {
+    const char *e = std::getenv("PIR_GROUPED_RING");
+    if (e && !std::strcmp(e, "deep")) return 1;
+    if (e && !std::strcmp(e, "wide")) return 2;
+    return 0;
+}
+
 // PIR_GROUPED_SHAPE="pts,rows,cols" forces one tile shape on every job
 // (returned as index + 1 into G_SHAPES; 0 = not forced or not a shape).
 static uint32_t forced_shape() {
@@ -1137,14 +1145,6 @@ struct EventPair {
     }
 };
 
-// PIR_GROUPED_RING=deep|wide restricts the rings (1 deep, 2 wide; 0 = both).
-static uint32_t forced_ring() {
-    const char *e = std::getenv("PIR_GROUPED_RING");
-    if (e && !std::strcmp(e, "deep")) return 1;
-    if (e && !std::strcmp(e, "wide")) return 2;
-    return 0;
-}
-
 static std::shared_ptr<GroupPlan> find_plan(const std::vector<std::pair<const pir_db *, uint32_t>> &key, int dev,
                                             uint32_t forced, uint32_t ring) {
     for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
@@ -1164,6 +1164,24 @@ MfmaJob make_shaped_job(const pir_db &db, const int8_t *qd, uint32_t *stage, uin
     j.nblk_n = (j.d1 + s.bn() - 1) / s.bn();
     j.tiles = j.groups * j.nblk_m * j.nblk_n;
     return j;
+}
+
+// Tile shape of one job of mp rows and d1 columns (serving steps):
+// PIR_GROUPED_SHAPE when set, else the fewest padded output words, the
+// fixed-shape kernel's shapes first on a tie; deep: it runs in
+// rowsel_mfma_persistent (a 192-row shape, unless PIR_GROUPED_RING=wide).
+void pick_shape(uint32_t mp, uint32_t d1, uint32_t *pts, uint32_t *wm, bool *deep) {
+    const size_t nshape = sizeof(G_SHAPES) / sizeof(G_SHAPES[0]);
+    uint32_t best = 0;
+    if (const uint32_t f = forced_shape()) {
+        best = f - 1;
+    } else {
+        for (uint32_t s2 = 1; s2 < nshape; ++s2)
+            if (shape_work(G_SHAPES[s2], mp, d1) < shape_work(G_SHAPES[best], mp, d1)) best = s2;
+    }
+    *pts = G_SHAPES[best].pts;
+    *wm = G_SHAPES[best].wm;
+    *deep = G_SHAPES[best].deep_ok() && forced_ring() != 2;
 }
 
 // A job of a grouped plan in tile shape `s`.

@@ -221,23 +221,17 @@ struct pir_server {
         // useful sub-tiles, 256 DB columns per pipeline stage)
         const uint32_t mp = (rows + 31) / 32 * 32;
         uint32_t pts = 1, wm = 2;
-        uint64_t best = UINT64_MAX;
-        for (const auto &sh : {std::pair<uint32_t, uint32_t>{1, 4}, {1, 2}, {1, 1}, {1, 8}, {2, 2}, {2, 1}, {2, 4}}) {
-            const uint64_t bm = 32 * sh.second, bn = 32 * (8 / (sh.first * sh.second));
-            const uint64_t w = (mp + bm - 1) / bm * bm * ((db->p.d1 + bn - 1) / bn * bn);
-            if (w < best) {
-                best = w;
-                pts = sh.first;
-                wm = sh.second;
-            }
-        }
+        bool deep = true;
+        pick_shape(mp, db->p.d1, &pts, &wm, &deep);
         MfmaJob job = make_shaped_job(*db, qd, stage, hi + 1, pts, wm);
         job.mstride = mstride;
         job.g_begin = g_begin;
         job.groups = ng;
         job.tiles = ng * job.nblk_m * job.nblk_n;
-        const bool deep = pts == 1 && (wm == 2 || wm == 4);   // the 192-row shapes take the three-stage ring
-        launch_mfma_grouped(job, nullptr, 1, job.tiles, job.split, deep, st);
+        {
+            KernelTimer::Scope timed(st);
+            launch_mfma_grouped(job, nullptr, 1, job.tiles, job.split, deep, st);
+        }
         const uint32_t cp = 4 * ng, nblk_n = (db->p.d1 + 63) / 64, nblk_p = (cp + 63) / 64;
         const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_p;
         PIR_REQUIRE(blocks < (1ull << 31), "scatter launch too large");

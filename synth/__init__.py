@@ -267,6 +267,13 @@ PAPER_Q108 = Workload("rowsel_n4096_l4q108_256x512_b32", 6, 4096, PRIMES_Q108, 2
                       "uniform", note="four 27-bit limbs (Q ~ 2^108) and D0 = 256 as in the paper's "
                       "setting; 8 GiB DB; one client and a batch of 32")
 
+# Offered loads of the serving workload, frozen: Poisson rates of 0.7x and
+# 0.9x the saturated rate (twice the 256-client admission cap arriving at
+# once) measured on one MI355X with this library, 2700 queries/s.
+SERVE_SATURATED_QPS = 2700.0
+SERVE_LOADS = (0.7, 0.9)
+SERVE_RATES_QPS = tuple(round(f * SERVE_SATURATED_QPS, 1) for f in SERVE_LOADS)
+
 GROUPED_SEED = 4
 GROUPED_COUNT = 24
 

@@ -51,6 +51,10 @@ SHAPES = [
     (8192, (1073692673,), 6, 3, 1),
     (16384, (1073643521,), 3, 2, 2),
     (256, synth.PRIMES_Q108, 20, 9, 3),
+    # many clients (the N = 4096 register form and the four-limb setting)
+    (4096, synth.PRIMES_N4096, 7, 5, 19),
+    (512, synth.PRIMES_Q108, 33, 10, 16),
+    (64, synth.PRIMES_N4096, 20, 12, 40),
 ]
 
 
