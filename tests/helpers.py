@@ -75,12 +75,12 @@ def host_db_ntt(seed, d0, d1, primes, n, sub=0, log=None):
     return oracle.ntt_db(coeffs, primes)
 
 
-def host_query(seed, B, d0, primes, n, sub=0):
+def host_query(seed, B, d0, primes, n, sub=0, tag=synth.TAG_QUERY):
     """synth.query_uniform for all B clients, clients generated in parallel."""
     out = np.empty((B, 2, d0, len(primes), n), dtype=np.uint32)
 
     def fill(b):
-        out[b] = synth.query_uniform(seed, B, d0, primes, n, sub=sub, clients=[b])[0]
+        out[b] = synth.query_uniform(seed, B, d0, primes, n, sub=sub, clients=[b], tag=tag)[0]
 
     with ThreadPoolExecutor(_workers()) as ex:
         list(ex.map(fill, range(B)))

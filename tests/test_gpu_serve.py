@@ -123,37 +123,48 @@ def test_serve_budget_bounds_capacity(pir, served):
         pir.pir_server_create(db, max_clients=4, hbm_budget=1024)
 
 
-def test_serve_full_size_sampled(pir):
-    """The serving workload's DB (N = 4096, two primes, 1024 x 1024, 32 GiB):
-    three requests from the seeded query pool, admitted while others run,
-    each checked against the oracle on two sampled DB columns."""
+@pytest.mark.timeout(900)
+def test_serve_full_size_every_word(pir):
+    """The serving workload's DB (N = 4096, two primes, 1024 x 1024, 32 GiB)
+    and its whole 32-query pool, served through pir_serve_step with 8 client
+    slots (requests arrive over several turns, so most are admitted while
+    others run); every output word of every request is compared with the
+    oracle, which regenerates the DB and the pool from their seeds and runs
+    its own NTT and RowSel on the host cores."""
+    import time
+    from helpers import device_db, host_db_ntt, host_query
     w = synth.SERVE_DB
-    print("building the 32 GiB serving DB", flush=True)
-    from helpers import device_db
+    print("device: building the 32 GiB serving DB", flush=True)
     db = device_db(pir, w.n, w.primes, w.d0, w.d1, w.seed, pir.PIR_LAYOUT_MFMA)
     pool = []
-    for i in range(3):
+    for i in range(32):
         q = empty_u32(2 * w.d0 * w.slots)
         pir.pir_synth_query(q, synth.stream_key(w.seed, synth.TAG_POOL, i), 0, 1, w.d0, w.primes, w.n)
         pool.append(q)
-    outs = [empty_u32(2 * w.d1 * w.slots) for _ in range(3)]
+    outs = [empty_u32(2 * w.d1 * w.slots) for _ in range(32)]
     srv = pir.pir_server_create(db, max_clients=8, chunks=16)
-    print("serving", flush=True)
-    got = run_until(pir, srv, {0: [(0, pool[0], outs[0])], 2: [(1, pool[1], outs[1]), (2, pool[2], outs[2])]}, 3,
-                    timeout=120.0)
+    schedule = {t: [(i, pool[i], outs[i]) for i in range(4 * t, 4 * t + 4)] for t in range(8)}
+    print("serving the 32 pool queries", flush=True)
+    got = run_until(pir, srv, schedule, 32, timeout=300.0)
     torch.cuda.synchronize()
+    st = pir.pir_server_get_stats(srv)
     pir.pir_server_destroy(srv)
-    cols = [3, w.d1 - 1]
-    coeffs = synth.db_coeffs(w.seed, w.d0, w.d1, 2, w.n, cols=cols)
-    dhat = oracle.ntt_db(coeffs, w.primes)
-    for i in range(3):
-        assert got[i].status == 0
-        # the pool query of request i, regenerated on the host from its seeded stream
-        qh = synth.query_uniform(w.seed, 1, w.d0, w.primes, w.n, sub=i, tag=synth.TAG_POOL)
-        want = oracle.rowsel(qh, dhat, w.primes)
-        out = np_u32(outs[i]).reshape(1, 2, w.d1, 2, w.n)[:, :, cols]
-        assert np.array_equal(out, want), f"request {i}"
     pir.pir_db_free(db)
+    del pool
+    assert all(got[i].status == 0 for i in range(32)) and st.completed == 32
+    t = time.time()
+    print("host: the oracle's NTT of the 32 GiB DB", flush=True)
+    dhat = host_db_ntt(w.seed, w.d0, w.d1, w.primes, w.n)
+    print(f"host: DB ready in {time.time() - t:.1f} s", flush=True)
+    for c0 in range(0, 32, 8):
+        # pool query i, regenerated on the host from its own seeded stream
+        qh = np.concatenate([host_query(w.seed, 1, w.d0, w.primes, w.n, sub=i, tag=synth.TAG_POOL)
+                             for i in range(c0, c0 + 8)])
+        want = oracle.rowsel(qh, dhat, w.primes)
+        for i in range(c0, c0 + 8):
+            got_i = np_u32(outs[i]).reshape(1, 2, w.d1, 2, w.n)
+            assert np.array_equal(got_i, want[i - c0: i - c0 + 1]), f"request {i}"
+        print(f"requests {c0}..{c0 + 7}: every word equals the oracle ({time.time() - t:.1f} s)", flush=True)
 
 
 def test_serve_duplicate_ids_rejected(pir, served):
