@@ -1061,7 +1061,7 @@ struct GShape {
     uint32_t wn() const { return NWAVE / (pts * wm); }
     uint32_t bm() const { return 32 * wm; }
     uint32_t bn() const { return 32 * wn(); }
-    // fits the three-stage 192-row ring
+    // a shape of rowsel_mfma_persistent (192 operand rows, three-stage ring)
     bool deep_ok() const { return pts * (bm() + bn()) == 192; }
 };
 static const GShape G_SHAPES[] = {{1, 4}, {1, 2}, {1, 1}, {1, 8}, {2, 2}, {2, 1}, {2, 4}};
