@@ -66,3 +66,31 @@ def test_noalloc_rejects_beyond_scratch(pir):
     with pytest.raises(pir.PirError, match="VALU layout"):
         pir.pir_rowsel_noalloc(mdb, empty_u32(2 * 4 * 2 * 64), empty_u32(2 * 8 * 2 * 64))
     pir.pir_db_free(mdb)
+
+
+def test_noalloc_under_graph_capture(pir):
+    """The allocation-free call captured into a hipGraph (its first call on
+    the device, outside capture, takes the scratch address): three replays
+    with eager work between them, each equal to pir_rowsel."""
+    db, q, want = _case(pir, 512, 40, 200, 2, 95)
+    ref = empty_u32(want.size)
+    pir.pir_rowsel(db, q, ref, pir.PIR_PATH_VALU)
+    out = empty_u32(want.size)
+    pir.pir_rowsel_noalloc(db, q, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pir.pir_rowsel_noalloc(db, q, out, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(rep + 7)                       # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep}"
+    assert np.array_equal(np_u32(out).reshape(want.shape), want)
+    del g
+    pir.pir_db_free(db)
