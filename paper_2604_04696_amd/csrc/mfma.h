@@ -53,6 +53,19 @@ void launch_mfma_grouped(const MfmaJob &one, const MfmaJob *jobs_dev, uint32_t n
 void pick_shape(uint32_t mp, uint32_t d1, uint32_t *pts, uint32_t *wm, bool *deep);
 // A job for that kernel in tile shape pts x 32wm x 32wn (pts * wm * wn = 8).
 MfmaJob make_shaped_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t B, uint32_t pts, uint32_t wm);
+// The query-resident kernel (rowsel_mfma_qres.hip) for mp <= 128 rows
+// (larger mp in 128-row blocks): shape 0 is 32 rows x 128 columns per work
+// unit, 1 is 64 x 128, 2 is 128 x 64.  Its query planes have mstride rows,
+// at least the job's row blocks times the shape's rows.
+uint32_t qres_shape_for(uint32_t mp);
+// whether a job of mp rows and nkc 64-row chunks of k runs in it
+bool qres_preferred(uint32_t mp, uint32_t nkc);
+uint32_t qres_rows(uint32_t shape);
+uint32_t qres_cols(uint32_t shape);
+uint32_t qres_min_chunks(uint32_t shape);   // 64-row chunks of k the kernel needs at least
+MfmaJob make_qres_job(const pir_db &db, const int8_t *qd, uint32_t mstride, uint32_t *stage, uint32_t B,
+                      uint32_t shape);
+void launch_mfma_qres(const MfmaJob &job, hipStream_t st);
 // Staging row stride of a DB with d1 columns (16-byte aligned rows).
 inline uint32_t staging_stride(uint32_t d1) { return (d1 + 3) / 4 * 4; }
 

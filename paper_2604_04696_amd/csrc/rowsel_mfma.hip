@@ -1023,7 +1023,10 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
     // scratch: query digit planes [P][4][Kp/64][Mp][64], then the output
     // staging [P][Mp][sstride]
     const uint32_t mp = (2 * B + 31) / 32 * 32;
-    const size_t qbytes = (mfma_query_scratch_bytes(db, B) + 255) / 256 * 256;
+    const bool qres = qres_preferred(mp, db.mfma.kp / 64);
+    const uint32_t shape = qres_shape_for(mp), bm = qres_rows(shape);
+    const uint32_t mstride = qres ? (mp + bm - 1) / bm * bm : mp;
+    const size_t qbytes = ((size_t)db.slots() * 4 * mstride * db.mfma.kp + 255) / 256 * 256;
     const size_t sbytes = (size_t)db.slots() * mp * staging_stride(db.p.d1) * 4;
     StreamScratch buf(qbytes + sbytes, st);
     int8_t *scratch = buf.as<int8_t>();
@@ -1033,12 +1036,16 @@ void launch_rowsel_mfma(const pir_db &db, const uint32_t *q, uint32_t B, uint32_
         // the usual ingest (scratch freed when the call's work has passed)
         StreamScratch qn((size_t)B * 2 * db.p.d0 * db.slots() * 4, st);
         launch_query_ntt(db, q, B, qn.as<uint32_t>(), st);
-        launch_query_digits(db, qn.as<uint32_t>(), B, scratch, st);
+        launch_query_digits_rows(db, qn.as<uint32_t>(), 2 * B, scratch, mstride, 0, st);
     } else {
-        launch_query_digits(db, q, B, scratch, st);
+        launch_query_digits_rows(db, q, 2 * B, scratch, mstride, 0, st);
     }
-    const MfmaJob job = make_mfma_job(db, scratch, stage, B, 0, pick_wm(B));
-    {
+    if (qres) {
+        const MfmaJob job = make_qres_job(db, scratch, mstride, stage, B, shape);
+        KernelTimer::Scope timed(st);
+        launch_mfma_qres(job, st);
+    } else {
+        const MfmaJob job = make_mfma_job(db, scratch, stage, B, 0, pick_wm(B));
         KernelTimer::Scope timed(st);
         launch_mfma_jobs(job, nullptr, 1, job.tiles, st);
     }

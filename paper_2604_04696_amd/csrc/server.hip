@@ -219,16 +219,25 @@ struct pir_server {
         // the tile shape that pads the fewest output words for this many rows
         // (32 x 256 while at most 16 clients are active: all eight waves on
         // useful sub-tiles, 256 DB columns per pipeline stage)
+        // (or the query-resident kernel when the rows fill its units)
         const uint32_t mp = (rows + 31) / 32 * 32;
-        uint32_t pts = 1, wm = 2;
-        bool deep = true;
-        pick_shape(mp, db->p.d1, &pts, &wm, &deep);
-        MfmaJob job = make_shaped_job(*db, qd, stage, hi + 1, pts, wm);
-        job.mstride = mstride;
-        job.g_begin = g_begin;
-        job.groups = ng;
-        job.tiles = ng * job.nblk_m * job.nblk_n;
-        {
+        MfmaJob job;
+        if (qres_preferred(mp, db->mfma.kp / 64)) {
+            job = make_qres_job(*db, qd, mstride, stage, hi + 1, qres_shape_for(mp));
+            job.g_begin = g_begin;
+            job.groups = ng;
+            job.tiles = 4 * ng * job.nblk_m * job.nblk_n;
+            KernelTimer::Scope timed(st);
+            launch_mfma_qres(job, st);
+        } else {
+            uint32_t pts = 1, wm = 2;
+            bool deep = true;
+            pick_shape(mp, db->p.d1, &pts, &wm, &deep);
+            job = make_shaped_job(*db, qd, stage, hi + 1, pts, wm);
+            job.mstride = mstride;
+            job.g_begin = g_begin;
+            job.groups = ng;
+            job.tiles = ng * job.nblk_m * job.nblk_n;
             KernelTimer::Scope timed(st);
             launch_mfma_grouped(job, nullptr, 1, job.tiles, job.split, deep, st);
         }
