@@ -144,11 +144,14 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
     // Query load j of a chunk moves 16 rows of one digit, placed at byte
     // v * 1024 of the buffer, v = wv + j * QWAVES = d * (BM / 16) + rb.  A
     // lane moves 16 bytes; chunk c of local row r sits at position
-    // c ^ ((r >> 2) & 3) (conflict-free fragment reads), hence the lane's
-    // source offset.
-    const uint32_t qlane = (lane / 4) * QKCH + ((lane % 4) ^ ((lane / 16) & 3)) * 16;
+    // c ^ ((r >> 1) & 3), hence the lane's source offset.  A fragment read
+    // (16 rows at one chunk index) is then free of bank conflicts; with
+    // c ^ ((r >> 2) & 3), the tiled kernel's swizzle for its 32-row
+    // fragments, every read here took two passes (counters: 4 conflict
+    // cycles per read, none with this one).
+    const uint32_t qlane = (lane / 4) * QKCH + ((lane % 4) ^ ((lane / 8) & 3)) * 16;
     const uint32_t arow = wr * 16 * RS + lane % 16;
-    const uint32_t a_lane = arow * QKCH + ((lane / 16) ^ ((arow >> 2) & 3)) * 16;
+    const uint32_t a_lane = arow * QKCH + ((lane / 16) ^ ((arow >> 1) & 3)) * 16;
     int8_t *const ring = lds + S::DB_LDS + wv * (RING * DBCH);
     auto q_base = [&](const QUnit &u) { return J.qd + u.p * 4 * qstride + (uint64_t)u.m0 * QKCH + qlane; };
     auto d_base = [&](const QUnit &u) {
@@ -277,21 +280,33 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
         i32x4 b[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) b[d] = *reinterpret_cast<const i32x4 *>(bb + d * 1024);
+        // query digit i's RS fragments go to buffer i % 2, two digits ahead
+        // of their MFMAs, so each digit's reads overlap the previous digit's
+        // MFMAs
         const int8_t *ab = lds + c_buf * QCH + a_lane;
         c_buf = c_buf + 1 == NQ ? 0 : c_buf + 1;
-        i32x4 a[RS];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        i32x4 a[2][RS];
+        auto read_a = [&](int i) {
 #pragma unroll
             for (int rs = 0; rs < RS; ++rs)
-                a[rs] = *reinterpret_cast<const i32x4 *>(ab + (i * BM + rs * 16) * QKCH);
-            __builtin_amdgcn_sched_barrier(0);
+                a[i % 2][rs] = *reinterpret_cast<const i32x4 *>(ab + (i * BM + rs * 16) * QKCH);
+        };
+        read_a(0);
+        read_a(1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int rs = 0; rs < RS; ++rs)
-                    acc[i + j][rs] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rs], b[j], acc[i + j][rs], 0, 0, 0);
+                    acc[i + j][rs] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i % 2][rs], b[j], acc[i + j][rs], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
+            if (i + 2 < 4) {
+                read_a(i + 2);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     };
 
