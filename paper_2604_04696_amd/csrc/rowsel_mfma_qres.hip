@@ -1,21 +1,22 @@
-// RowSel on the INT8 matrix cores, query-resident form, for 64 or 128 query
-// rows (2B = 33..64 or 97..128; more rows run in 128-row blocks).
+// RowSel on the INT8 matrix cores, query-resident form, for 64 to 128 query
+// rows (2B = 33..64; more rows run in 128-row blocks).
 //
 // The arithmetic is that of rowsel_mfma.hip (four balanced signed digits per
 // residue, sixteen digit products summed per weight class s = i + j in int32,
 // exact binary64 recombination per output, a class flush every 2048 rows of
 // k).  What differs is the data flow and the MFMA shape.  A work unit is one
 // point, BM query rows and BN DB columns; every wave owns RS sub-tiles of
-// 16 x 16 outputs stacked along m and one 16-column slice of the DB, which it
-// loads itself into a private LDS ring (four digits x 16 columns x 64 rows
-// of k, 4 KiB per chunk) and multiplies against the RS query fragments with
-// v_mfma_i32_16x16x64_i8, so one DB fragment feeds RS MFMAs per digit pair
-// and the DB needs no exchange between waves.  The query chunk of a step is
-// shared by the block through a small LDS ring.  Shapes (RS, WR = row groups
-// of waves): (4, 1) 64 x 128 and (4, 2) 128 x 64 (the two row groups load
-// the same DB columns); (2, 1) 32 x 128 is kept for tuning (with 32 rows it
-// ties with the tiled kernel).  Every wave holds seven class accumulators
-// per sub-tile, 112 registers with RS = 4, as in the tiled kernel.
+// 16 x 16 outputs stacked along m over one 16-column slice of the DB and
+// multiplies its four B fragments (one per DB digit) against the RS query
+// fragments of each query digit with v_mfma_i32_16x16x64_i8, so a DB
+// fragment feeds RS MFMAs per digit pair.  Per 64-row chunk of k the block
+// copies the query chunk (four digits x BM rows) and the DB chunk into LDS
+// rings; with one row group (64 x 128 units) each wave loads its own 16
+// columns into a ring of its own, with two (128 x 64 units) the block shares
+// one DB ring, since both row groups read the same columns.  (2, 1) 32 x 128
+// is kept for tuning: with 32 rows it ties with the tiled kernel.  Every wave
+// holds seven class accumulators per sub-tile, 112 registers with RS = 4, as
+// in the tiled kernel.
 //
 // Operand layout of v_mfma_i32_16x16x64_i8: lane l supplies row (A) or
 // column (B) l % 16 and the 16 bytes of k-group l / 16 of the 64-row chunk;
@@ -45,22 +46,28 @@ constexpr uint32_t QKSUPER = 2048;                  // rows of k per int32 accum
 
 // RS 16-row sub-tiles per wave, WR row groups of waves, NQ query chunk
 // buffers per block, RING DB chunks per wave (RING - 1 = PF in flight).
-template <int RS_, int WR_, int NQ_, int RING_>
+// SHDB: one DB ring for the block (the row groups share the columns),
+// else one per wave.
+template <int RS_, int WR_, int NQ_, int RING_, bool SHDB_ = false>
 struct QShape {
     static constexpr int RS = RS_;
     static constexpr int WR = WR_;
     static constexpr int NQ = NQ_;
     static constexpr int RING = RING_;
+    static constexpr bool SHDB = SHDB_;
     static constexpr int PF = RING - 1;
     static constexpr int BM = 16 * RS * WR;              // query rows of a unit
     static constexpr int WC = QWAVES / WR;               // waves per row group
     static constexpr int BN = 16 * WC;                   // DB columns of a unit
     static constexpr int QCH = 4 * BM * QKCH;            // bytes of one query chunk (four digits)
     static constexpr int QL = QCH / 1024 / QWAVES;       // 1 KiB query loads per wave and chunk
-    static constexpr int DB_LDS = NQ * QCH;              // offset of the DB rings
+    static constexpr int DBS = SHDB ? 4 * BN * QKCH : QWAVES * DBCH;   // bytes of one DB ring slot, all waves
+    static constexpr int DL = SHDB ? DBS / 1024 / QWAVES : 4;          // 1 KiB DB loads per wave and chunk
+    static constexpr int DB_LDS = NQ * QCH;              // offset of the DB ring
     static_assert(QL >= 1 && QL * QWAVES * 1024 == QCH, "query chunk loads");
-    static_assert(DB_LDS + QWAVES * RING * DBCH <= LDS_BYTES, "LDS");
-    static_assert(PF >= 1 && PF <= NQ && NQ >= 2 && PF >= NQ - 1, "pipeline depths");
+    static_assert(DL >= 1 && (!SHDB || DL * QWAVES * 1024 == DBS), "DB chunk loads");
+    static_assert(DB_LDS + RING * DBS <= LDS_BYTES, "LDS");
+    static_assert(PF >= 1 && (SHDB || (PF <= NQ && PF >= NQ - 1)) && NQ >= 2, "pipeline depths");
 };
 
 template <int N>
@@ -99,36 +106,37 @@ __device__ __forceinline__ QUnit decode_unit(uint32_t u, const MfmaJob &J, uint3
 // query planes in that XCD's L2.
 //
 // LDS: a ring of NQ query chunks (all four digits of BM rows for 64 rows of
-// k) shared by the block and, per wave, a ring of RING 4 KiB DB chunks (four
-// digits of the wave's 16 columns).  Every operand moves global -> LDS with
-// global_load_lds_dwordx4 and every wait for those loads is explicit: a
-// wave's vector-memory operations retire in issue order, so a wave waits for
-// a load by waiting until no more than the count issued after it are
-// outstanding.  Chunk step t of a block:
+// k) shared by the block and a ring of RING DB chunks (four digits of the
+// unit's columns; per wave, its 16 columns, or shared).  Every operand moves
+// global -> LDS with global_load_lds_dwordx4 and every wait for those loads
+// is explicit: a wave's vector-memory operations retire in issue order, so a
+// wave waits for a load by waiting until no more than the count issued after
+// it are outstanding.  Chunk step t of a block:
 //   1. waits for its loads of query chunk t (issued NQ - 1 steps earlier;
 //      everything issued before them is then done too, which is at most
-//      DB chunk t - NQ + PF <= t: nothing the step does not need anyway)
-//      and meets the block at a barrier, after which the query buffer read
-//      in step t - 1 is free;
-//   2. issues its loads of query chunk t + NQ - 1 into that buffer and of
-//      its DB chunk t + PF into its ring;
-//   3. waits for its DB chunk t (PF steps' loads were issued after it;
-//      in the first PF steps it waits for everything);
-//   4. reads the four digits' B fragments from its ring and, per query
-//      digit, the RS A fragments, and issues 16 RS v_mfma_i32_16x16x64_i8
-//      into the seven class accumulators.
-// The DB thus streams PF chunks ahead per wave (up to 96 KiB per CU in
-// flight, which is what sets the streaming rate with few query rows) with no
-// barrier of its own.  Both load cursors run over the block's units ahead of
-// the MFMAs; the host requires nkc >= NQ - 1 and nkc >= PF so that neither is
-// more than one unit ahead, and past the last unit they reload their last
-// chunk into buffers nobody reads.
+//      DB chunk t - NQ + PF <= t: nothing the step does not need anyway) --
+//      with the shared DB ring also for its loads of DB chunk t -- and meets
+//      the block at a barrier, after which the buffers read in step t - 1
+//      are free;
+//   2. issues its loads of query chunk t + NQ - 1 and of DB chunk t + PF
+//      (PF = RING - 1) into those buffers;
+//   3. with its own DB ring, waits for its DB chunk t (PF steps' loads were
+//      issued after it; in the first PF steps it waits for everything);
+//   4. reads the four digits' B fragments and, per query digit, the RS A
+//      fragments (the next digit's read while the MFMAs of this one run),
+//      and issues 16 RS v_mfma_i32_16x16x64_i8 into the seven class
+//      accumulators.
+// A wave's own DB ring streams PF chunks ahead with no barrier of its own.
+// Both load cursors run over the block's units ahead of the MFMAs; the host
+// requires nkc >= NQ - 1 and nkc >= PF so that neither is more than one unit
+// ahead, and past the last unit they reload their last chunk into buffers
+// nobody reads.
 template <class S, int MODE>
 __global__ void __launch_bounds__(64 * QWAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))
 rowsel_mfma_qres_kernel(const MfmaJob J) {
     constexpr int RS = S::RS, WR = S::WR, BM = S::BM, BN = S::BN, NQ = S::NQ, RING = S::RING, PF = S::PF;
-    constexpr int QCH = S::QCH, QL = S::QL;
-    constexpr int DBL = 4;   // DB loads per chunk step
+    constexpr int QCH = S::QCH, QL = S::QL, DBL = S::DL, DBS = S::DBS;
+    constexpr bool SHDB = S::SHDB;
     __shared__ __attribute__((aligned(1024))) int8_t lds[LDS_BYTES];
 
     const uint32_t lane = threadIdx.x % 64;
@@ -152,10 +160,25 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
     const uint32_t qlane = (lane / 4) * QKCH + ((lane % 4) ^ ((lane / 8) & 3)) * 16;
     const uint32_t arow = wr * 16 * RS + lane % 16;
     const uint32_t a_lane = arow * QKCH + ((lane / 16) ^ ((arow >> 1) & 3)) * 16;
-    int8_t *const ring = lds + S::DB_LDS + wv * (RING * DBCH);
+    // DB ring: per wave, slot k of wave w at k * DBS + w * 4 KiB, digit d
+    // at + d KiB, the lane's 16 bytes at + lane * 16 (what it loaded itself);
+    // shared, slot k at k * DBS, digit d at + d * BN * 64, column c at + c * 64
+    // with the same chunk swizzle as the query (load v of a chunk is 16
+    // columns of one digit: v = d * (BN / 16) + cq).
+    int8_t *const ring = lds + S::DB_LDS + (SHDB ? 0 : wv * DBCH);
+    const uint32_t bcol = wc * 16 + lane % 16;
+    const uint32_t b_lane = SHDB ? bcol * QKCH + ((lane / 16) ^ ((bcol >> 1) & 3)) * 16 : lane * 16;
     auto q_base = [&](const QUnit &u) { return J.qd + u.p * 4 * qstride + (uint64_t)u.m0 * QKCH + qlane; };
-    auto d_base = [&](const QUnit &u) {
-        const uint32_t n = u.n0 + wc * 16 + lane % 16;   // columns past D1: never stored
+    // per-lane source of DB load j (columns past D1 are never stored); a
+    // wave's own ring takes the four digits at one source plus j digit planes
+    constexpr int DP = SHDB ? DBL : 1;
+    auto d_base = [&](const QUnit &u, int j) {
+        if (SHDB) {
+            const uint32_t v = wv + j * QWAVES, d = v / (BN / 16), cq = v % (BN / 16);
+            const uint32_t n = u.n0 + cq * 16 + lane / 4;
+            return J.dbd + u.p * 4 * dstride + d * dstride + (uint64_t)min(n, d1 - 1) * QKCH + (qlane % QKCH);
+        }
+        const uint32_t n = u.n0 + wc * 16 + lane % 16;
         return J.dbd + u.p * 4 * dstride + (uint64_t)min(n, d1 - 1) * QKCH + (lane / 16) * 16;
     };
     // the unit after iteration i (iteration i's own past the last one)
@@ -196,21 +219,27 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
 
     // ---- DB cursor: chunk d_kc of the unit at d_cur, into ring slot d_slot
     // (as the query cursor)
-    const int8_t *d_cur = d_base(cu), *d_nxt = d_base(nu);
+    const int8_t *d_cur[DP], *d_nxt[DP];
+#pragma unroll
+    for (int j = 0; j < DP; ++j) {
+        d_cur[j] = d_base(cu, j);
+        d_nxt[j] = d_base(nu, j);
+    }
     uint32_t d_kc = 0, d_slot = 0;
     bool d_last = q_last;
     auto d_issue = [&]() {
         if (d_kc == nkc && !d_last) {
-            d_cur = d_nxt;
+#pragma unroll
+            for (int j = 0; j < DP; ++j) d_cur[j] = d_nxt[j];
             d_kc = 0;
             d_last = true;
         }
-        const int8_t *src = d_cur + min(d_kc, nkc - 1) * dplane;
-        int8_t *dst = ring + d_slot * DBCH;
+        const uint64_t off = min(d_kc, nkc - 1) * dplane;
+        int8_t *dst = ring + d_slot * DBS;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const int8_t *from = src + d * dstride;
-            lds_void *to = (lds_void *)(dst + d * 1024);
+        for (int j = 0; j < DBL; ++j) {
+            const int8_t *from = SHDB ? d_cur[j % DP] + off : d_cur[0] + off + j * dstride;
+            lds_void *to = (lds_void *)(dst + (SHDB ? (wv + j * QWAVES) : j) * 1024);
             __builtin_amdgcn_global_load_lds(from, to, 16, 0, 0);
         }
         d_slot = d_slot + 1 == RING ? 0 : d_slot + 1;
@@ -262,24 +291,39 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
     uint32_t c_buf = 0, c_slot = 0;   // query buffer and LDS ring slot of the chunk being computed
     uint32_t gstep = 0;               // chunk steps of this block so far
 
+    // loads issued after the later of this wave's loads of query chunk t
+    // (step t - NQ + 1, first in its step) and of DB chunk t (step t - PF,
+    // second): with a shared DB ring both must have landed at the barrier
+    constexpr int AFTER_BOTH = PF > NQ - 1 ? DBL + (NQ - 2) * (QL + DBL) : (PF - 1) * (QL + DBL);
     auto step = [&]() {
-        // 1. query chunk t: after its loads, this wave issued one step's DB
-        //    loads and NQ - 2 steps' query and DB loads
-        qwait_vmcnt<DBL + (NQ - 2) * (QL + DBL)>();
-        qbarrier();
-        // 2.
-        q_issue();
-        d_issue();
-        // 3. DB chunk t: PF steps' loads were issued after it
-        if (gstep < PF) qwait_vmcnt<0>();
-        else qwait_vmcnt<PF * (QL + DBL)>();
-        ++gstep;
+        if constexpr (SHDB) {
+            // 1. this wave's loads of query and DB chunk t, then everybody's
+            if (gstep < (uint32_t)(PF > NQ ? PF : NQ)) qwait_vmcnt<0>();
+            else qwait_vmcnt<AFTER_BOTH>();
+            ++gstep;
+            qbarrier();
+            // 2.
+            q_issue();
+            d_issue();
+        } else {
+            // 1. query chunk t: after its loads, this wave issued one step's
+            //    DB loads and NQ - 2 steps' query and DB loads
+            qwait_vmcnt<DBL + (NQ - 2) * (QL + DBL)>();
+            qbarrier();
+            // 2.
+            q_issue();
+            d_issue();
+            // 3. DB chunk t: PF steps' loads were issued after it
+            if (gstep < PF) qwait_vmcnt<0>();
+            else qwait_vmcnt<PF * (QL + DBL)>();
+            ++gstep;
+        }
         // 4.
-        const int8_t *bb = ring + c_slot * DBCH + lane * 16;
+        const int8_t *bb = ring + c_slot * DBS + b_lane;
         c_slot = c_slot + 1 == RING ? 0 : c_slot + 1;
         i32x4 b[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) b[d] = *reinterpret_cast<const i32x4 *>(bb + d * 1024);
+        for (int d = 0; d < 4; ++d) b[d] = *reinterpret_cast<const i32x4 *>(bb + d * (SHDB ? BN * QKCH : 1024));
         // query digit i's RS fragments go to buffer i % 2, two digits ahead
         // of their MFMAs, so each digit's reads overlap the previous digit's
         // MFMAs
@@ -325,7 +369,8 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
         nu = next_unit(ci);
         const bool more = unit_of(ci + 1) < units;
         q_nxt = q_base(nu);
-        d_nxt = d_base(nu);
+#pragma unroll
+        for (int j = 0; j < DP; ++j) d_nxt[j] = d_base(nu, j);
         q_last = !more;
         d_last = !more;
     }
@@ -344,8 +389,9 @@ int qres_cu_count() {
 
 }  // namespace
 
-// Unit shapes (RS, WR; query buffers, DB ring): 32 x 128, 64 x 128,
-// 128 x 64.
+// Unit shapes (RS, WR; query buffers, DB ring slots): 32 x 128, 64 x 128,
+// 128 x 64 (one DB ring for the block: per-wave rings, which load each
+// column twice, made the 64-client GEMM 4.28 ms against 4.16).
 struct QVariant {
     uint32_t rs, wr, nq, ring;
     uint32_t rows() const { return 16 * rs * wr; }
@@ -357,16 +403,16 @@ constexpr uint32_t NQRES = sizeof(QRES) / sizeof(QRES[0]);
 uint32_t qres_min_chunks(uint32_t shape) { return QRES[shape].min_chunks(); }
 
 // PIR_MFMA_KERNEL=qres or tile forces a kernel, else the query-resident one
-// when the rows fill its 64- or 128-row units (measured on the 512 x 512,
-// N = 4096 DB: 64 rows 2.25 ms against 2.43 ms tiled, 128 rows 4.50 against
-// 4.70; 32 rows is a tie, and 96 rows, half a row group idle, is slower).
+// for 64, 96 and 128 rows (measured on the 512 x 512, N = 4096 DB: 64 rows
+// 2.17 ms against 2.43 ms tiled, 96 rows 3.89 against 4.02, 128 rows 4.16
+// against 4.61; with 32 rows the two tie).
 bool qres_preferred(uint32_t mp, uint32_t nkc) {
     if (nkc < qres_min_chunks(qres_shape_for(mp))) return false;
     if (const char *e = std::getenv("PIR_MFMA_KERNEL")) {
         if (!std::strcmp(e, "qres")) return true;
         if (!std::strcmp(e, "tile")) return false;
     }
-    return mp == 64 || mp == 128;
+    return mp >= 64 && mp <= 128;
 }
 
 uint32_t qres_shape_for(uint32_t mp) {
@@ -416,7 +462,7 @@ void launch_mfma_qres(const MfmaJob &job, hipStream_t st) {
     switch (job.wm) {
         case 0: go_mode(QShape<2, 1, 3, 4>{}); break;
         case 1: go_mode(QShape<4, 1, 3, 3>{}); break;
-        default: go_mode(QShape<4, 2, 2, 3>{}); break;
+        default: go_mode(QShape<4, 2, 2, 3, true>{}); break;
     }
     PIR_LAUNCH_CHECK();
 }

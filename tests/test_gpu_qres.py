@@ -4,8 +4,8 @@ oracle, word for word, and against the tiled MFMA kernel on the same inputs.
 
 PIR_MFMA_KERNEL=qres forces single pir_rowsel calls on the MFMA path through
 it (PIR_MFMA_KERNEL=tile through the tiled kernel).  The shapes cover its
-three unit shapes (32 x 128, 64 x 128 and 128 x 64, picked from the padded
-row count) and more than 128 rows (units in several row blocks), D1 ragged
+three unit shapes (32 x 128 and 64 x 128 with a DB ring per wave, 128 x 64
+with one per block; picked from the padded row count, or forced taller) and more than 128 rows (units in several row blocks), D1 ragged
 against every unit width, D0 at the fewest chunks of k the kernel takes, D0
 above the 2048-row int32 accumulation (flushes that add to what an earlier
 flush of the unit stored), the split and wide recombination forms, four
@@ -134,4 +134,23 @@ def test_qres_coefficient_domain_query(pir, monkeypatch):
     torch.cuda.synchronize()
     assert_guards(guard)
     assert np.array_equal(np_u32(out).reshape(want.shape), want)
+    pir.pir_db_free(db)
+
+
+FORCED = [(s, 2) for s in SHAPES if 2 * s[4] <= 64] + [((16, P2, 200, 20, 30), 2)] + \
+         [(s, 1) for s in SHAPES if 2 * s[4] <= 32]
+
+
+@pytest.mark.parametrize("shape,variant", FORCED,
+                         ids=[f"N{s[0]}L{len(s[1])}_{s[2]}x{s[3]}_B{s[4]}_u{v}" for s, v in FORCED])
+def test_qres_larger_units(pir, shape, variant, monkeypatch):
+    """Rows in units taller than they need (PIR_QRES_VARIANT picks the unit
+    shape): 128-row units, whose two row groups share one DB ring, and 64-row
+    units, with half or more of their rows past the batch."""
+    say("qres larger units", shape, variant)
+    monkeypatch.setenv("PIR_QRES_VARIANT", str(variant))
+    db, q, want = _case(pir, shape)
+    got = _run(pir, db, q, want.size, "qres", monkeypatch)
+    g = np_u32(got).reshape(want.shape)
+    assert np.array_equal(g, want), f"{(g != want).sum()} of {want.size} words differ"
     pir.pir_db_free(db)
