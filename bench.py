@@ -137,15 +137,20 @@ def grouped_section(pir, reps: int):
     graph = statistics.median(timed_calls(g.replay, reps))
     res = {"instances": len(insts), "mod_macs": macs, "db_gib": round(dbb / 2**30, 2),
            "eager_ms": round(eager, 3), "graph_ms": round(graph, 3),
-           "mac_per_s": macs / (graph * 1e-3), "db_gbs": round(dbb / (graph * 1e-3) / 1e9, 1),
-           "launches": 2 * len(insts) + 1}
-    tiles = pir.pir_rowsel_grouped_tiles(items)
-    res["tiles"] = [f"{p}x{m}x{n}" for p, m, n in tiles]   # points x rows x columns per instance
-    res["tile_note"] = "per instance, timed at plan build among the shapes within 25% of the fewest padded words"
+           "mac_per_s": macs / (graph * 1e-3), "db_gbs": round(dbb / (graph * 1e-3) / 1e9, 1)}
+    plan = pir.pir_rowsel_grouped_tiles(items)
+    # points x rows x columns per instance, its kernel, "+" when its GEMM has a launch of its own
+    res["tiles"] = [f"{pir.GROUPED_KERNELS[k]}:{p}x{m}x{n}{'+' if alone else ''}" for p, m, n, k, alone in plan]
+    shared = {(k, m) for p, m, n, k, alone in plan if not alone and k == 0} | \
+             {k for p, m, n, k, alone in plan if not alone and k == 1}
+    res["launches"] = 2 * len(insts) + len(shared) + sum(alone for *_, alone in plan)
+    res["tile_note"] = ("per instance, timed at plan build: fixed-shape and shaped tiled kernels (shapes within "
+                        "25% of the fewest padded words) and the query-resident kernel; shared launches or one "
+                        "per instance, timed")
     # output words the GEMM computes (tile padding included) against the
     # 2B x D1 it needs, per point and K row (query rows are padded to 32)
     useful = computed = 0
-    for it, (p, m, n) in zip(insts, tiles):
+    for it, (p, m, n, _, _) in zip(insts, plan):
         mp = (2 * it.clients + 31) // 32 * 32
         useful += 2 * it.clients * it.d1 * it.d0
         computed += (mp + m - 1) // m * m * ((it.d1 + n - 1) // n * n) * it.d0

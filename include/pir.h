@@ -226,8 +226,8 @@ typedef struct {
  * the current device; outputs of distinct items must not overlap one another
  * or any query.  Results equal `count` separate pir_rowsel calls bit for
  * bit.  MFMA path (PIR_PATH_MFMA_I8, or AUTO when every DB holds the MFMA
- * layout): one query-ingest launch per item, ONE persistent GEMM launch over
- * the output tiles of all items, one output-transpose launch per item.  VALU
+ * layout): one query-ingest launch per item, the GEMM launches of the
+ * item list's plan (below), one output-transpose launch per item.  VALU
  * path: the items' RowSel launches back to back.
  * The first MFMA call for a given list of (db, B) allocates a plan (device
  * work table and scratch, kept for reuse) and must not be made while the
@@ -237,29 +237,38 @@ typedef struct {
  * (least recently used ones are released beyond that); a plan used under
  * capture is kept until one of its DBs is freed, so a captured graph stays
  * valid until pir_db_free of one of its items' DBs.
- * Tiles: each item gets its own tile shape, `points` NTT points side by side
- * x `rows` GEMM rows x `columns` DB columns, from 1 x 128x64, 1 x 64x128,
- * 1 x 32x256, 1 x 256x32, 2 x 64x64, 2 x 32x128 and 2 x 128x32 (eight 32x32
- * MFMA sub-tiles each).  When the plan is built, every item's shapes within
- * 25% of the fewest padded output words run once, alone, on the call's own
- * inputs, timed on its stream (the first call therefore synchronizes the
- * stream), and the fastest is kept.  PIR_AUTOTUNE=0 in the environment keeps
- * the shape with the fewest padded words without timing;
- * PIR_GROUPED_SHAPE="points,rows,columns" forces one shape on every item.
- * Two pipeline rings exist: three stages of 192 operand rows (the 1 x 128x64
- * and 1 x 64x128 shapes) and two stages of 320 rows (every shape); the items
- * of each ring run in one persistent launch (two GEMM launches at most), and
- * the timing above covers both rings for the 192-row shapes.
- * PIR_GROUPED_RING=deep or wide restricts the choice to one ring. */
+ * Plan: each item gets its own kernel and tile shape.  Candidates: the
+ * fixed-shape tiled kernel (1 x 128x64 and 1 x 64x128 tiles, three stages of
+ * 192 operand rows), the shaped tiled kernel (`points` NTT points side by
+ * side x `rows` GEMM rows x `columns` DB columns: 1 x 128x64, 1 x 64x128,
+ * 1 x 32x256, 1 x 256x32, 2 x 64x64, 2 x 32x128, 2 x 128x32, two stages of
+ * 320 rows; those within 25% of the fewest padded output words) and the
+ * query-resident kernel (units of 1 x 32x128, 1 x 64x128, 1 x 128x64; items
+ * whose D0 spans at least two or three 64-row chunks).  When the plan is
+ * built every candidate runs three times, alone, on the call's own inputs, timed on
+ * its stream (the first call therefore synchronizes the stream), and the
+ * fastest is kept.  The tiled items then run either in one persistent launch
+ * per tiled kernel and tile family (three at most) or in one launch each,
+ * whichever of the two schedules ran faster at plan build; each
+ * query-resident item has a launch of its own.  PIR_AUTOTUNE=0 in the
+ * environment keeps the candidate with the fewest padded words and the
+ * shared launches without timing; PIR_GROUPED_SHAPE="points,rows,columns"
+ * forces one tiled shape on every item; PIR_GROUPED_RING=deep, wide or qres
+ * restricts the candidates to the fixed-shape, the shaped or (where D0
+ * allows) the query-resident kernel; PIR_GROUPED_SCHED=shared or split
+ * forces a schedule.  The results are the same bit for bit in every case. */
 pir_status pir_rowsel_grouped(const pir_rowsel_item *items, uint32_t count,
                               pir_path path, void *hip_stream);
 
-/* Tile shapes chosen for the cached MFMA plan of an item list, as built by a
- * previous pir_rowsel_grouped call with the same list of (db, B): tiles[3i],
- * tiles[3i+1], tiles[3i+2] = points, rows, columns of item i (zeros for an
- * item with B = 0).  Only the (db, B) pairs of `items` are read; `tiles`
- * holds 3*count words.  PIR_EINVAL if no plan exists for the list or a
- * pointer is NULL. */
+/* The plan an item list's MFMA calls run, as built by a previous
+ * pir_rowsel_grouped call with the same list of (db, B): for item i,
+ * tiles[5i .. 5i+4] = points, rows, columns of its tile or work unit, its
+ * kernel (0 fixed-shape tiled, 1 shaped tiled, 2 query-resident) and 1 if
+ * its GEMM has a launch of its own, 0 if it shares one (zeros for an item
+ * with B = 0).  Only the (db, B) pairs of `items` are read; `tiles` holds
+ * PIR_GROUPED_TILE_WORDS * count words.  PIR_EINVAL if no plan exists for
+ * the list or a pointer is NULL. */
+#define PIR_GROUPED_TILE_WORDS 5
 pir_status pir_rowsel_grouped_tiles(const pir_rowsel_item *items, uint32_t count, uint32_t *tiles);
 
 /* ---------------------------------------------------------------- serving */

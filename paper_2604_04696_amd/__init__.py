@@ -275,16 +275,23 @@ def pir_rowsel_grouped(items, path: int = PIR_PATH_AUTO, stream=None):
                                     _stream(stream)), "pir_rowsel_grouped")
 
 
+PIR_GROUPED_TILE_WORDS = 5
+GROUPED_KERNELS = ("fixed", "shaped", "qres")   # kernel ids of pir_rowsel_grouped_tiles
+
+
 def pir_rowsel_grouped_tiles(items):
-    """[(points, rows, cols)] of the tile kept for each item of the plan of
-    this item list ((0, 0, 0) for B = 0 items)."""
+    """[(points, rows, cols, kernel, alone)] of the plan of this item list:
+    the tile or work unit kept for each item, its kernel (0 fixed-shape
+    tiled, 1 shaped tiled, 2 query-resident) and whether its GEMM has a
+    launch of its own ((0, 0, 0, 0, 0) for B = 0 items)."""
+    w = PIR_GROUPED_TILE_WORDS
     arr = (pir_rowsel_item * max(1, len(items)))()
     for i, (db, q, B, out) in enumerate(items):
         arr[i].db, arr[i].B = db.handle, B
-    t = (_u32 * max(3, 3 * len(items)))()
+    t = (_u32 * max(w, w * len(items)))()
     _check(lib().pir_rowsel_grouped_tiles(ctypes.cast(arr, ctypes.c_void_p), len(items), t),
            "pir_rowsel_grouped_tiles")
-    return [(t[3 * i], t[3 * i + 1], t[3 * i + 2]) for i in range(len(items))]
+    return [tuple(t[w * i + j] for j in range(w)) for i in range(len(items))]
 
 
 # ---------------------------------------------------------------- serving

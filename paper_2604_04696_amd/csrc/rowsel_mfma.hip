@@ -1084,14 +1084,19 @@ struct GroupPlan {
     bool pinned = false;
     uint32_t forced = 0;            // shape forced by PIR_GROUPED_SHAPE (index + 1), 0 = chosen
     uint32_t ring_forced = 0;       // PIR_GROUPED_RING: 1 deep, 2 wide, 0 = chosen
+    uint32_t sched_forced = 0;      // PIR_GROUPED_SCHED: 1 shared launches, 2 one per job, 0 = timed
     int8_t *scratch = nullptr;
     MfmaJob *jobs_dev = nullptr;
     // jobs in launch order: 128x64 tiles of the fixed-shape kernel, then its
-    // 64x128 tiles, then the shaped kernel's jobs; launch g covers jobs
-    // [first[g], first[g+1]) with tiles numbered from 0
+    // 64x128 tiles, then the shaped kernel's jobs, then the query-resident
+    // kernel's; in the shared schedule launch g < 3 covers jobs
+    // [first[g], first[g+1]) with tiles numbered from 0, and every
+    // query-resident job [first[3], first[4]) has a launch of its own
     std::vector<MfmaJob> jobs;
+    std::vector<uint8_t> kind;      // per job: G_DEEP, G_WIDE or G_QRES
     std::vector<size_t> item_job;   // item -> job index, or SIZE_MAX for B = 0
-    uint32_t first[4] = {0, 0, 0, 0}, tiles[3] = {0, 0, 0}, split = RECOMB_DIRECT;
+    uint32_t first[5] = {0, 0, 0, 0, 0}, tiles[3] = {0, 0, 0}, split = RECOMB_DIRECT;
+    bool per_job = false;           // one GEMM launch per job instead of one per kernel
     ~GroupPlan() {
         if (scratch) {
             int prev = 0;
@@ -1120,11 +1125,27 @@ static void evict_plans_locked() {
     }
 }
 
-// PIR_GROUPED_RING=deep|wide restricts the rings (1 deep, 2 wide; 0 = both).
+// Kernels of a grouped job: the fixed-shape kernel (three-stage 192-row
+// ring), the shaped kernel (two-stage 320-row ring), the query-resident
+// kernel (rowsel_mfma_qres.hip).
+enum : uint8_t { G_DEEP = 0, G_WIDE = 1, G_QRES = 2 };
+
+// PIR_GROUPED_RING=deep|wide|qres restricts the candidates to one kernel
+// (1 deep, 2 wide, 3 query-resident where it fits; 0 = all).
 static uint32_t forced_ring() {
     const char *e = std::getenv("PIR_GROUPED_RING");
     if (e && !std::strcmp(e, "deep")) return 1;
     if (e && !std::strcmp(e, "wide")) return 2;
+    if (e && !std::strcmp(e, "qres")) return 3;
+    return 0;
+}
+
+// PIR_GROUPED_SCHED=shared|split forces the GEMM launch schedule (1 one
+// launch per kernel, 2 one launch per job; 0 = timed at plan build).
+static uint32_t forced_sched() {
+    const char *e = std::getenv("PIR_GROUPED_SCHED");
+    if (e && !std::strcmp(e, "shared")) return 1;
+    if (e && !std::strcmp(e, "split")) return 2;
     return 0;
 }
 
@@ -1153,9 +1174,10 @@ struct EventPair {
 };
 
 static std::shared_ptr<GroupPlan> find_plan(const std::vector<std::pair<const pir_db *, uint32_t>> &key, int dev,
-                                            uint32_t forced, uint32_t ring) {
+                                            uint32_t forced, uint32_t ring, uint32_t sched) {
     for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
-        if ((*it)->key == key && (*it)->device == dev && (*it)->forced == forced && (*it)->ring_forced == ring) {
+        if ((*it)->key == key && (*it)->device == dev && (*it)->forced == forced && (*it)->ring_forced == ring &&
+            (*it)->sched_forced == sched) {
             g_plans.splice(g_plans.begin(), g_plans, it);
             return g_plans.front();
         }
@@ -1196,27 +1218,48 @@ static MfmaJob grouped_job(const pir_db &db, const int8_t *qd, uint32_t *stage, 
     return make_shaped_job(db, qd, stage, B, s.pts, s.wm);
 }
 
+static void launch_plan_gemms(const GroupPlan &pl, hipStream_t st);
+
 // Builds the plan of a new item set.  Candidates of a job: the two 192-row
-// shapes in rowsel_mfma_persistent (the "deep" ring: three stages) and the
+// shapes in rowsel_mfma_persistent (the "deep" ring: three stages), the
 // shapes within 25% of the fewest padded output words in the shaped kernel
-// (the "wide" ring).  Without timing (PIR_AUTOTUNE=0) the job takes the
-// candidate with the fewest padded words (the fixed-shape kernel on a tie);
-// otherwise every candidate runs twice, alone, on the job's own inputs (the
-// query digit planes are built first), timed with events on the call's
-// stream, and the fastest is kept for every later call.  The jobs then go to
-// up to three persistent launches (fixed-shape 128x64, fixed-shape 64x128,
-// shaped kernel), all taking the widest recombination form any job needs
-// (each form is exact for the primes of the narrower ones).
+// (the "wide" ring) and the query-resident kernel's unit shapes (32 x 128,
+// 64 x 128, 128 x 64; its query planes take rows in blocks of 128, so every
+// job whose K fits it gets planes of a multiple of 128 rows; the rows past
+// 2B are never written and only feed output rows that are dropped).
+// Without timing (PIR_AUTOTUNE=0) the job takes the candidate with the
+// fewest padded words (the fixed-shape kernel on a tie); otherwise every
+// candidate runs three times, alone, on the job's own inputs (the query digit
+// planes are built first), timed with events on the call's stream, and the
+// fastest is kept for every later call.  The jobs of the two tiled kernels
+// then run either in up to three shared persistent launches (fixed-shape
+// 128x64, fixed-shape 64x128, shaped kernel, all taking the widest
+// recombination form any job needs: each form is exact for the primes of
+// the narrower ones) or in one launch per job; the query-resident jobs
+// always run one launch each.  With timing both schedules run three times and the
+// faster is kept (jobs that share a launch also share its persistent
+// blocks, but their point groups then compete for the L2 of each XCD).
 static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
+    const uint32_t ring_forced = pl.ring_forced;
+    // query-resident unit shapes a job of nkc chunks of k can take
+    auto qres_shapes = [&](uint32_t nkc) {
+        std::vector<uint32_t> v;
+        if (pl.forced || ring_forced == 1 || ring_forced == 2) return v;
+        for (uint32_t s2 = 0; s2 < 3; ++s2)
+            if (nkc >= qres_min_chunks(s2)) v.push_back(s2);
+        return v;
+    };
     // scratch: per job [query digits][staging], then the job tables
     std::vector<size_t> qoff(count, 0), soff(count, 0);
+    std::vector<uint32_t> mst(count, 0);
     size_t bytes = 0;
     for (uint32_t i = 0; i < count; ++i) {
         if (!items[i].B) continue;
         const pir_db &db = *items[i].db;
-        const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32;
+        const uint32_t mp = (2 * items[i].B + 31) / 32 * 32;
+        mst[i] = qres_shapes(db.mfma.kp / KCH).empty() ? mp : (mp + 127) / 128 * 128;
         qoff[i] = bytes;
-        bytes += (mfma_query_scratch_bytes(db, items[i].B) + 255) / 256 * 256;
+        bytes += ((size_t)db.slots() * 4 * mst[i] * db.mfma.kp + 255) / 256 * 256;
         soff[i] = bytes;
         bytes += ((size_t)db.slots() * mp * staging_stride(db.p.d1) * 4 + 255) / 256 * 256;
     }
@@ -1225,105 +1268,168 @@ static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t cou
     pl.scratch = static_cast<int8_t *>(dev_alloc(bytes));
     pl.jobs_dev = reinterpret_cast<MfmaJob *>(pl.scratch + jobs_off);
 
-    // candidate (shape, ring) pairs of each job
+    // candidates of each job: (shape, kernel); shape indexes G_SHAPES, or
+    // for G_QRES the query-resident unit shape
     const size_t nshape = sizeof(G_SHAPES) / sizeof(G_SHAPES[0]);
-    const uint32_t ring_forced = pl.ring_forced;
-    struct Cand { uint32_t shape; bool deep; };
+    struct Cand { uint32_t shape; uint8_t kind; uint64_t work; };
     std::vector<std::vector<Cand>> cands(count);
+    auto make_job = [&](uint32_t i, const Cand &c) {
+        const pir_db &db = *items[i].db;
+        int8_t *qd = pl.scratch + qoff[i];
+        uint32_t *stage = reinterpret_cast<uint32_t *>(pl.scratch + soff[i]);
+        MfmaJob j = c.kind == G_QRES ? make_qres_job(db, qd, mst[i], stage, items[i].B, c.shape)
+                                     : grouped_job(db, qd, stage, items[i].B, G_SHAPES[c.shape]);
+        j.mstride = mst[i];
+        return j;
+    };
     std::vector<size_t> qj;   // item of each job
     std::vector<MfmaJob> jobs;
+    std::vector<uint8_t> kind;
     for (uint32_t i = 0; i < count; ++i) {
         if (!items[i].B) continue;
         const pir_db &db = *items[i].db;
         const uint64_t mp = (2ull * items[i].B + 31) / 32 * 32, d1 = db.p.d1;
-        std::vector<uint32_t> order(nshape);
-        for (uint32_t s2 = 0; s2 < nshape; ++s2) order[s2] = s2;
-        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-            return shape_work(G_SHAPES[a], mp, d1) < shape_work(G_SHAPES[b], mp, d1);
-        });
-        const uint64_t best = shape_work(G_SHAPES[order[0]], mp, d1);
-        std::vector<uint32_t> shapes;
-        if (pl.forced) shapes.push_back(pl.forced - 1);
-        else
-            for (uint32_t s2 : order)
-                if (shape_work(G_SHAPES[s2], mp, d1) * 4 <= best * 5) shapes.push_back(s2);
-        if (!pl.forced && ring_forced != 2)   // the fixed-shape kernel's two shapes, always tried
-            for (uint32_t s2 = 0; s2 < nshape; ++s2)
-                if (G_SHAPES[s2].deep_ok()) cands[i].push_back({s2, true});
-        for (uint32_t s2 : shapes) {
-            if (pl.forced && G_SHAPES[s2].deep_ok() && ring_forced != 2) cands[i].push_back({s2, true});
-            if (ring_forced != 1 || !G_SHAPES[s2].deep_ok()) cands[i].push_back({s2, false});
-        }
-        if (!pl.forced) {   // the geometric best first when not timing
-            std::stable_sort(cands[i].begin(), cands[i].end(), [&](const Cand &a, const Cand &b) {
-                return shape_work(G_SHAPES[a.shape], mp, d1) < shape_work(G_SHAPES[b.shape], mp, d1);
+        std::vector<Cand> &cs = cands[i];
+        const std::vector<uint32_t> qs = qres_shapes(db.mfma.kp / KCH);
+        if (ring_forced == 3 && !qs.empty()) {
+            for (uint32_t s2 : qs) {
+                const uint64_t bm = qres_rows(s2), bn = qres_cols(s2);
+                cs.push_back({s2, G_QRES, (mp + bm - 1) / bm * bm * ((d1 + bn - 1) / bn * bn)});
+            }
+        } else {
+            std::vector<uint32_t> order(nshape);
+            for (uint32_t s2 = 0; s2 < nshape; ++s2) order[s2] = s2;
+            std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+                return shape_work(G_SHAPES[a], mp, d1) < shape_work(G_SHAPES[b], mp, d1);
             });
+            const uint64_t best = shape_work(G_SHAPES[order[0]], mp, d1);
+            std::vector<uint32_t> shapes;
+            if (pl.forced) shapes.push_back(pl.forced - 1);
+            else
+                for (uint32_t s2 : order)
+                    if (shape_work(G_SHAPES[s2], mp, d1) * 4 <= best * 5) shapes.push_back(s2);
+            // (a ring forced to the query-resident kernel that the job's K
+            // does not fit leaves every tiled candidate)
+            if (!pl.forced && ring_forced != 2)   // the fixed-shape kernel's two shapes, always tried
+                for (uint32_t s2 = 0; s2 < nshape; ++s2)
+                    if (G_SHAPES[s2].deep_ok()) cs.push_back({s2, G_DEEP, shape_work(G_SHAPES[s2], mp, d1)});
+            for (uint32_t s2 : shapes) {
+                const uint64_t w = shape_work(G_SHAPES[s2], mp, d1);
+                if (pl.forced && G_SHAPES[s2].deep_ok() && ring_forced != 2) cs.push_back({s2, G_DEEP, w});
+                if (ring_forced != 1 || !G_SHAPES[s2].deep_ok()) cs.push_back({s2, G_WIDE, w});
+            }
+            for (uint32_t s2 : qs) {
+                const uint64_t bm = qres_rows(s2), bn = qres_cols(s2);
+                cs.push_back({s2, G_QRES, (mp + bm - 1) / bm * bm * ((d1 + bn - 1) / bn * bn)});
+            }
         }
+        if (!pl.forced)   // the geometric best first when not timing
+            std::stable_sort(cs.begin(), cs.end(), [](const Cand &a, const Cand &b) { return a.work < b.work; });
         qj.push_back(i);
-        jobs.push_back(grouped_job(db, pl.scratch + qoff[i], reinterpret_cast<uint32_t *>(pl.scratch + soff[i]),
-                                   items[i].B, G_SHAPES[cands[i][0].shape]));
+        jobs.push_back(make_job(i, cs[0]));
+        kind.push_back(cs[0].kind);
     }
-    std::vector<uint8_t> deep(jobs.size());
-    for (size_t k = 0; k < jobs.size(); ++k) deep[k] = cands[qj[k]][0].deep;
     pl.item_job.assign(count, SIZE_MAX);
     if (jobs.empty()) return;
     pl.split = RECOMB_DIRECT;
     for (const MfmaJob &j : jobs) pl.split = std::max(pl.split, j.split);
 
+    // one job alone in its own launch
+    auto launch_alone = [&](MfmaJob j, uint8_t k) {
+        j.split = pl.split;
+        if (k == G_QRES) {
+            launch_mfma_qres(j, st);
+        } else {
+            j.tile0 = 0;
+            launch_mfma_grouped(j, nullptr, 1, j.tiles, pl.split, k == G_DEEP, st);
+        }
+    };
+    EventPair ev;
+    auto time_ms = [&](auto &&enqueue) {
+        float best = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {
+            PIR_HIP(hipEventRecord(ev.a, st));
+            enqueue();
+            PIR_HIP(hipEventRecord(ev.b, st));
+            PIR_HIP(hipEventSynchronize(ev.b));
+            float t = 0.0f;
+            PIR_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+            best = rep ? std::min(best, t) : t;
+        }
+        return best;
+    };
+
     const char *tune = std::getenv("PIR_AUTOTUNE");
     const bool timing = !pl.forced && !(tune && std::strcmp(tune, "0") == 0);
     if (timing) {
         for (size_t k = 0; k < jobs.size(); ++k)
-            launch_query_digits(*items[qj[k]].db, items[qj[k]].q_dev, items[qj[k]].B,
-                                const_cast<int8_t *>(jobs[k].qd), st);
-        EventPair ev;
+            launch_query_digits_rows(*items[qj[k]].db, items[qj[k]].q_dev, 2 * items[qj[k]].B,
+                                     const_cast<int8_t *>(jobs[k].qd), jobs[k].mstride, 0, st);
         for (size_t k = 0; k < jobs.size(); ++k) {
             const uint32_t i = (uint32_t)qj[k];
             if (cands[i].size() < 2) continue;
             float best = 0.0f;
             bool first = true;
             for (const Cand &c : cands[i]) {
-                MfmaJob probe = grouped_job(*items[i].db, jobs[k].qd, jobs[k].out, items[i].B, G_SHAPES[c.shape]);
+                MfmaJob probe = make_job(i, c);
                 probe.split = pl.split;
-                float ms = 0.0f;
-                for (int rep = 0; rep < 2; ++rep) {
-                    PIR_HIP(hipEventRecord(ev.a, st));
-                    launch_mfma_grouped(probe, nullptr, 1, probe.tiles, pl.split, c.deep, st);
-                    PIR_HIP(hipEventRecord(ev.b, st));
-                    PIR_HIP(hipEventSynchronize(ev.b));
-                    float t = 0.0f;
-                    PIR_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
-                    ms = rep ? std::min(ms, t) : t;
-                }
+                const float ms = time_ms([&] { launch_alone(probe, c.kind); });
                 if (first || ms < best) {
                     best = ms;
                     jobs[k] = probe;
-                    deep[k] = c.deep;
+                    kind[k] = c.kind;
                     first = false;
                 }
             }
         }
     }
-    // launch order: fixed-shape 128x64, fixed-shape 64x128, shaped kernel;
-    // tile numbers restart at 0 in each launch
-    for (int g = 0; g < 3; ++g) {
+    // launch order: fixed-shape 128x64, fixed-shape 64x128, shaped kernel,
+    // query-resident kernel; tile numbers restart at 0 in each launch
+    for (int g = 0; g < 4; ++g) {
         pl.first[g] = (uint32_t)pl.jobs.size();
         uint32_t tile0 = 0;
         for (size_t k = 0; k < jobs.size(); ++k) {
-            const int gk = !deep[k] ? 2 : jobs[k].wm == 4 ? 0 : 1;
+            const int gk = kind[k] == G_QRES ? 3 : kind[k] == G_WIDE ? 2 : jobs[k].wm == 4 ? 0 : 1;
             if (gk != g) continue;
             MfmaJob j = jobs[k];
-            j.tile0 = tile0;
+            j.tile0 = g < 3 ? tile0 : 0;
             j.split = pl.split;
             tile0 += j.tiles;
             pl.item_job[qj[k]] = pl.jobs.size();
             pl.jobs.push_back(j);
+            pl.kind.push_back(kind[k]);
         }
-        pl.tiles[g] = tile0;
+        if (g < 3) pl.tiles[g] = tile0;
     }
-    pl.first[3] = (uint32_t)pl.jobs.size();
+    pl.first[4] = (uint32_t)pl.jobs.size();
     PIR_HIP(hipMemcpyAsync(pl.jobs_dev, pl.jobs.data(), sizeof(MfmaJob) * pl.jobs.size(), hipMemcpyHostToDevice, st));
     PIR_HIP(hipStreamSynchronize(st));
+    pl.per_job = pl.sched_forced == 2;
+    if (timing && !pl.sched_forced) {
+        pl.per_job = false;
+        const float shared = time_ms([&] { launch_plan_gemms(pl, st); });
+        pl.per_job = true;
+        const float alone = time_ms([&] { launch_plan_gemms(pl, st); });
+        pl.per_job = alone < shared;
+    }
+}
+
+// The GEMM launches of a plan, in its schedule.
+static void launch_plan_gemms(const GroupPlan &pl, hipStream_t st) {
+    for (int g = 0; g < 3; ++g) {
+        if (pl.first[g + 1] == pl.first[g]) continue;
+        if (pl.per_job) {
+            for (uint32_t k = pl.first[g]; k < pl.first[g + 1]; ++k) {
+                MfmaJob j = pl.jobs[k];
+                j.tile0 = 0;
+                launch_mfma_grouped(j, nullptr, 1, j.tiles, pl.split, g < 2, st);
+            }
+        } else {
+            launch_mfma_grouped(pl.jobs[pl.first[g]], pl.jobs_dev + pl.first[g], pl.first[g + 1] - pl.first[g],
+                                pl.tiles[g], pl.split, g < 2, st);
+        }
+    }
+    for (uint32_t k = pl.first[3]; k < pl.first[4]; ++k) launch_mfma_qres(pl.jobs[k], st);
 }
 
 // The plan of an item list (built on first use).  The caller holds a
@@ -1331,13 +1437,13 @@ static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t cou
 static std::shared_ptr<GroupPlan> get_plan(const pir_rowsel_item *items, uint32_t count, hipStream_t st) {
     std::vector<std::pair<const pir_db *, uint32_t>> key(count);
     for (uint32_t i = 0; i < count; ++i) key[i] = {items[i].db, items[i].B};
-    const uint32_t forced = forced_shape(), ring = forced_ring();
+    const uint32_t forced = forced_shape(), ring = forced_ring(), sched = forced_sched();
     int dev = 0;
     PIR_HIP(hipGetDevice(&dev));
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     PIR_HIP(hipStreamIsCapturing(st, &cap));
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    if (auto pl = find_plan(key, dev, forced, ring)) {
+    if (auto pl = find_plan(key, dev, forced, ring, sched)) {
         if (cap != hipStreamCaptureStatusNone) pl->pinned = true;
         return pl;
     }
@@ -1348,6 +1454,7 @@ static std::shared_ptr<GroupPlan> get_plan(const pir_rowsel_item *items, uint32_
     pl->device = dev;
     pl->forced = forced;
     pl->ring_forced = ring;
+    pl->sched_forced = sched;
     build_plan(*pl, items, count, st);   // on failure the plan frees what it allocated
     g_plans.push_front(pl);
     evict_plans_locked();
@@ -1368,13 +1475,22 @@ bool group_plan_tiles(const pir_rowsel_item *items, uint32_t count, uint32_t *ti
         }
     if (!pl) return false;
     for (uint32_t i = 0; i < count; ++i) {
-        uint32_t *t = tiles + 3 * i;
-        t[0] = t[1] = t[2] = 0;
+        uint32_t *t = tiles + PIR_GROUPED_TILE_WORDS * i;
+        for (int w = 0; w < PIR_GROUPED_TILE_WORDS; ++w) t[w] = 0;
         if (pl->item_job[i] == SIZE_MAX) continue;
-        const MfmaJob &j = pl->jobs[pl->item_job[i]];
-        t[0] = j.pts;
-        t[1] = 32 * j.wm;
-        t[2] = 32 * (NWAVE / (j.pts * j.wm));
+        const size_t k = pl->item_job[i];
+        const MfmaJob &j = pl->jobs[k];
+        if (pl->kind[k] == G_QRES) {
+            t[0] = 1;
+            t[1] = qres_rows(j.wm);
+            t[2] = qres_cols(j.wm);
+        } else {
+            t[0] = j.pts;
+            t[1] = 32 * j.wm;
+            t[2] = 32 * (NWAVE / (j.pts * j.wm));
+        }
+        t[3] = pl->kind[k];
+        t[4] = pl->kind[k] == G_QRES || pl->per_job;
     }
     return true;
 }
@@ -1384,15 +1500,14 @@ void launch_rowsel_mfma_grouped(const pir_rowsel_item *items, uint32_t count, hi
     GroupPlan &pl = *plan;
     if (pl.jobs.empty()) return;
     for (uint32_t i = 0; i < count; ++i)
-        if (pl.item_job[i] != SIZE_MAX)
-            launch_query_digits(*items[i].db, items[i].q_dev, items[i].B,
-                                const_cast<int8_t *>(pl.jobs[pl.item_job[i]].qd), st);
+        if (pl.item_job[i] != SIZE_MAX) {
+            const MfmaJob &j = pl.jobs[pl.item_job[i]];
+            launch_query_digits_rows(*items[i].db, items[i].q_dev, 2 * items[i].B, const_cast<int8_t *>(j.qd),
+                                     j.mstride, 0, st);
+        }
     {
         KernelTimer::Scope timed(st);
-        for (int g = 0; g < 3; ++g)
-            if (pl.first[g + 1] > pl.first[g])
-                launch_mfma_grouped(pl.jobs[pl.first[g]], pl.jobs_dev + pl.first[g], pl.first[g + 1] - pl.first[g],
-                                    pl.tiles[g], pl.split, g < 2, st);
+        launch_plan_gemms(pl, st);
     }
     for (uint32_t i = 0; i < count; ++i) {
         if (pl.item_job[i] == SIZE_MAX) continue;

@@ -81,6 +81,7 @@ def test_grouped_graph_replay(pir):
 
 
 SHAPES = [(1, 128, 64), (1, 64, 128), (1, 32, 256), (1, 256, 32), (2, 64, 64), (2, 32, 128), (2, 128, 32)]
+QRES_UNITS = [(1, 32, 128), (1, 64, 128), (1, 128, 64)]
 
 
 def test_grouped_tile_choice(pir, monkeypatch):
@@ -100,11 +101,11 @@ def test_grouped_tile_choice(pir, monkeypatch):
         tiles = pir.pir_rowsel_grouped_tiles(items)
         for (db, q, B, out), want, t in zip(items, wants, tiles):
             if not B:
-                assert t == (0, 0, 0) and np.all(np_u32(out) == 0xFFFFFFFF)
+                assert t == (0, 0, 0, 0, 0) and np.all(np_u32(out) == 0xFFFFFFFF)
                 continue
-            assert t in SHAPES
+            assert (t[3] < 2 and t[:3] in SHAPES) or (t[3] == 2 and t[:3] in QRES_UNITS and t[4] == 1)
             if forced:
-                assert ",".join(map(str, t)) == forced
+                assert ",".join(map(str, t[:3])) == forced and t[3] < 2
             assert np.array_equal(np_u32(out)[: want.size].reshape(want.shape), want), (forced, tune, t)
     monkeypatch.delenv("PIR_GROUPED_SHAPE")
     monkeypatch.delenv("PIR_AUTOTUNE")
@@ -143,7 +144,7 @@ def test_grouped_shape_long_k_and_extremes(pir, monkeypatch, shape, ring):
         wants.append(want)
     pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
     torch.cuda.synchronize()
-    assert all(t == shape for t in pir.pir_rowsel_grouped_tiles(items))
+    assert all(t[:3] == shape and t[3] == (0 if ring == "deep" else 1) for t in pir.pir_rowsel_grouped_tiles(items))
     for (db, q, B, out), want, guard in zip(items, wants, guards):
         assert np.array_equal(np_u32(out).reshape(want.shape), want), (shape, ring)
         assert_guards(guard)
@@ -206,3 +207,86 @@ def test_grouped_graph_survives_other_plans_and_frees(pir):
             if B:
                 got = np_u32(out)[: want.size].reshape(want.shape)
                 assert np.array_equal(got, want), f"replay {rep} differs"
+
+
+@pytest.mark.parametrize("sched", ["shared", "split"])
+@pytest.mark.parametrize("ring,tune", [("qres", ""), ("qres", "0"), ("", "")], ids=["qres", "qres-untimed", "any"])
+def test_grouped_kernels_and_schedules(pir, monkeypatch, ring, tune, sched):
+    """The query-resident kernel in grouped plans (forced on every item whose
+    D0 spans enough 64-row chunks: the others keep a tiled kernel) and both
+    GEMM schedules (shared persistent launches, one launch per item), against
+    the oracle word for word, then replayed from a captured graph."""
+    monkeypatch.setenv("PIR_GROUPED_RING", ring)
+    monkeypatch.setenv("PIR_AUTOTUNE", tune)
+    monkeypatch.setenv("PIR_GROUPED_SCHED", sched)
+    print("grouped kernels", ring, tune, sched, flush=True)
+    items, wants = _small_items(pir)
+    pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    plan = pir.pir_rowsel_grouped_tiles(items)
+    for (db, q, B, out), want, t, (n, d0, d1, _) in zip(items, wants, plan, SMALL):
+        if not B:
+            assert t == (0, 0, 0, 0, 0)
+            continue
+        if ring == "qres":
+            assert (t[3] == 2) == (d0 > 64), (d0, t)
+        assert t[4] == (1 if t[3] == 2 or sched == "split" else 0), t
+        assert np.array_equal(np_u32(out)[: want.size].reshape(want.shape), want), (ring, tune, sched, t)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for _, _, B, out in items:
+            if B:
+                out.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (db, q, B, out), want in zip(items, wants):
+            if B:
+                assert np.array_equal(np_u32(out)[: want.size].reshape(want.shape), want), f"replay {rep}"
+    del g
+    for db, *_ in items:
+        pir.pir_db_free(db)
+
+
+@pytest.mark.parametrize("sched", ["shared", "split"])
+def test_grouped_qres_long_k_and_extremes(pir, monkeypatch, sched):
+    """The query-resident kernel in a grouped plan on a K of 4100 rows (flushes
+    that add to what an earlier flush stored), all-(q-1) residues (every
+    output D0 mod q), more than 128 rows (two row blocks) and ragged D1."""
+    monkeypatch.setenv("PIR_GROUPED_RING", "qres")
+    monkeypatch.setenv("PIR_GROUPED_SCHED", sched)
+    primes = synth.PRIMES_N4096
+    n = 16
+    cases = [(4100, 37, 5, "ones"), (4100, 70, 70, "uniform"), (300, 200, 9, "uniform"), (130, 33, 17, "ones")]
+    items, wants, guards = [], [], []
+    for i, (k, d1, B, kind) in enumerate(cases):
+        if kind == "ones":
+            dhat = np.broadcast_to(np.array(primes, np.uint32)[None, None, :, None] - 1, (k, d1, 2, n)).copy()
+            query = np.broadcast_to(np.array(primes, np.uint32)[None, None, None, :, None] - 1,
+                                    (B, 2, k, 2, n)).copy()
+        else:
+            dhat = oracle.ntt_db(synth.db_coeffs(80 + i, k, d1, 2, n), primes)
+            query = synth.query_uniform(90 + i, B, k, primes, n)
+        db = pir.pir_db_create(pir.make_params(n, primes, k, d1), pir.PIR_LAYOUT_MFMA)
+        pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+        guard, out = guarded_u32(B * 2 * d1 * 2 * n)
+        guards.append(guard)
+        items.append((db, to_dev(query), B, out))
+        want = oracle.rowsel(query, dhat, primes)
+        if kind == "ones":
+            assert np.all(want == np.array([k % q for q in primes], np.uint32)[None, None, None, :, None])
+        wants.append(want)
+    print("grouped qres long k", sched, flush=True)
+    pir.pir_rowsel_grouped(items, pir.PIR_PATH_MFMA_I8)
+    torch.cuda.synchronize()
+    assert all(t[3] == 2 and t[4] == 1 for t in pir.pir_rowsel_grouped_tiles(items))
+    for (db, q, B, out), want, guard in zip(items, wants, guards):
+        assert np.array_equal(np_u32(out).reshape(want.shape), want), sched
+        assert_guards(guard)
+    for db, *_ in items:
+        pir.pir_db_free(db)
