@@ -287,7 +287,10 @@ typedef struct pir_server pir_server;
 typedef struct {
     uint32_t max_clients;   /* admission cap (slots), 1..4096; 0 = 256 */
     uint32_t chunks;        /* sweep steps per pass over the DB, 1..L*N/4; 0 = 16 */
-    uint32_t pipeline;      /* steps kept in flight on the device, 1..4; 0 = 2 */
+    uint32_t pipeline;      /* steps kept in flight on the device, 1..4; 0 = 1 (a request
+                             * admitted at a step boundary joins the next step; with
+                             * 2, one step later, for the same throughput on the
+                             * 32 GiB benchmark DB) */
     uint32_t max_waiting;   /* requests that may wait for a slot; an arrival that
                                finds this many waiting completes at once with
                                PIR_EBUSY (others go on); 0 = no bound */

@@ -112,7 +112,7 @@ struct pir_server {
     const pir_db *db = nullptr;
     int device = 0;
     hipStream_t st = nullptr;
-    uint32_t capacity = 0, chunks = 0, pipeline = 2, cg = 0, gall = 0, mstride = 0, max_waiting = 0;
+    uint32_t capacity = 0, chunks = 0, pipeline = 1, cg = 0, gall = 0, mstride = 0, max_waiting = 0;
     uint64_t device_bytes = 0;
     int8_t *qd = nullptr;
     uint32_t *stage = nullptr;
@@ -291,7 +291,7 @@ pir_status pir_server_create(const pir_db *db, const pir_server_opts *opts, pir_
         try {
             srv->db = db;
             srv->device = db->device;
-            srv->pipeline = o.pipeline ? o.pipeline : 2;
+            srv->pipeline = o.pipeline ? o.pipeline : 1;
             srv->max_waiting = o.max_waiting;
             srv->gall = (uint32_t)(db->slots() / 4);
             uint32_t chunks = o.chunks ? o.chunks : 16;
