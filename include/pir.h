@@ -243,10 +243,11 @@ typedef struct {
  * side x `rows` GEMM rows x `columns` DB columns: 1 x 128x64, 1 x 64x128,
  * 1 x 32x256, 1 x 256x32, 2 x 64x64, 2 x 32x128, 2 x 128x32, two stages of
  * 320 rows; those within 25% of the fewest padded output words) and the
- * query-resident kernel (units of 1 x 32x128, 1 x 64x128, 1 x 128x64; items
- * whose D0 spans at least two or three 64-row chunks).  When the plan is
- * built every candidate runs three times, alone, on the call's own inputs, timed on
- * its stream (the first call therefore synchronizes the stream), and the
+ * query-resident kernel (units of 1 x 32x128, 1 x 64x128, 1 x 96x64 and
+ * 1 x 128x64; items whose D0 spans at least two or three 64-row chunks).
+ * When the plan is built every candidate runs three times, alone, on the
+ * call's own inputs, timed on its stream (the first call therefore
+ * synchronizes the stream), and the
  * fastest is kept.  The tiled items then run either in one persistent launch
  * per tiled kernel and tile family (three at most) or in one launch each,
  * whichever of the two schedules ran faster at plan build; each

@@ -54,9 +54,11 @@ void pick_shape(uint32_t mp, uint32_t d1, uint32_t *pts, uint32_t *wm, bool *dee
 // A job for that kernel in tile shape pts x 32wm x 32wn (pts * wm * wn = 8).
 MfmaJob make_shaped_job(const pir_db &db, const int8_t *qd, uint32_t *out, uint32_t B, uint32_t pts, uint32_t wm);
 // The query-resident kernel (rowsel_mfma_qres.hip) for mp <= 128 rows
-// (larger mp in 128-row blocks): shape 0 is 32 rows x 128 columns per work
-// unit, 1 is 64 x 128, 2 is 128 x 64.  Its query planes have mstride rows,
-// at least the job's row blocks times the shape's rows.
+// (larger mp in row blocks of the unit's height): unit shape 0 is 32 rows x
+// 128 columns, 1 is 64 x 128, 2 is 96 x 64, 3 is 128 x 64 (shapes
+// [0, qres_shape_count())).  Its query planes have mstride rows, at least
+// the job's row blocks times the shape's rows.
+uint32_t qres_shape_count();
 uint32_t qres_shape_for(uint32_t mp);
 // whether a job of mp rows and nkc 64-row chunks of k runs in it
 bool qres_preferred(uint32_t mp, uint32_t nkc);

@@ -1276,9 +1276,9 @@ static void launch_plan_gemms(const GroupPlan &pl, hipStream_t st);
 // shapes in rowsel_mfma_persistent (the "deep" ring: three stages), the
 // shapes within 25% of the fewest padded output words in the shaped kernel
 // (the "wide" ring) and the query-resident kernel's unit shapes (32 x 128,
-// 64 x 128, 128 x 64; its query planes take rows in blocks of 128, so every
-// job whose K fits it gets planes of a multiple of 128 rows; the rows past
-// 2B are never written and only feed output rows that are dropped).
+// 64 x 128, 96 x 64, 128 x 64; a job whose K fits it gets query planes with
+// rows for the row blocks of each of those units; the rows past 2B are
+// never written and only feed output rows that are dropped).
 // Without timing (PIR_AUTOTUNE=0) the job takes the candidate with the
 // fewest padded words (the fixed-shape kernel on a tie); otherwise every
 // candidate runs three times, alone, on the job's own inputs (the query digit
@@ -1297,7 +1297,7 @@ static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t cou
     auto qres_shapes = [&](uint32_t nkc) {
         std::vector<uint32_t> v;
         if (pl.forced || ring_forced == 1 || ring_forced == 2) return v;
-        for (uint32_t s2 = 0; s2 < 3; ++s2)
+        for (uint32_t s2 = 0; s2 < qres_shape_count(); ++s2)
             if (nkc >= qres_min_chunks(s2)) v.push_back(s2);
         return v;
     };
@@ -1309,7 +1309,9 @@ static void build_plan(GroupPlan &pl, const pir_rowsel_item *items, uint32_t cou
         if (!items[i].B) continue;
         const pir_db &db = *items[i].db;
         const uint32_t mp = (2 * items[i].B + 31) / 32 * 32;
-        mst[i] = qres_shapes(db.mfma.kp / KCH).empty() ? mp : (mp + 127) / 128 * 128;
+        mst[i] = mp;   // rows for every candidate's row blocks
+        for (uint32_t s2 : qres_shapes(db.mfma.kp / KCH))
+            mst[i] = std::max(mst[i], (mp + qres_rows(s2) - 1) / qres_rows(s2) * qres_rows(s2));
         qoff[i] = bytes;
         bytes += ((size_t)db.slots() * 4 * mst[i] * db.mfma.kp + 255) / 256 * 256;
         soff[i] = bytes;

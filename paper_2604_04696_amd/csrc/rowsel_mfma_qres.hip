@@ -1,22 +1,23 @@
 // RowSel on the INT8 matrix cores, query-resident form, for 64 to 128 query
-// rows (2B = 33..64; more rows run in 128-row blocks).
+// rows (2B = 33..64; more rows run in blocks of the unit's height).
 //
 // The arithmetic is that of rowsel_mfma.hip (four balanced signed digits per
 // residue, sixteen digit products summed per weight class s = i + j in int32,
 // exact binary64 recombination per output, a class flush every 2048 rows of
 // k).  What differs is the data flow and the MFMA shape.  A work unit is one
-// point, BM query rows and BN DB columns; every wave owns RS sub-tiles of
-// 16 x 16 outputs stacked along m over one 16-column slice of the DB and
-// multiplies its four B fragments (one per DB digit) against the RS query
-// fragments of each query digit with v_mfma_i32_16x16x64_i8, so a DB
-// fragment feeds RS MFMAs per digit pair.  Per 64-row chunk of k the block
+// point, BM query rows and BN DB columns; every wave owns RS x RN sub-tiles
+// of 16 x 16 outputs (RS along m, RN along n) and multiplies its B fragments
+// (per DB digit, one per 16 columns) against the RS query fragments of each
+// query digit with v_mfma_i32_16x16x64_i8, so a DB fragment feeds RS and a
+// query fragment RN MFMAs per digit pair.  Per 64-row chunk of k the block
 // copies the query chunk (four digits x BM rows) and the DB chunk into LDS
-// rings; with one row group (64 x 128 units) each wave loads its own 16
-// columns into a ring of its own, with two (128 x 64 units) the block shares
-// one DB ring, since both row groups read the same columns.  (2, 1) 32 x 128
-// is kept for tuning: with 32 rows it ties with the tiled kernel.  Every wave
-// holds seven class accumulators per sub-tile, 112 registers with RS = 4, as
-// in the tiled kernel.
+// rings; with one row group of waves (units of 32 or 64 rows x 128 columns)
+// each wave loads its own 16 columns into a ring of its own, with several
+// (96 x 64 and 128 x 64 units) the block shares one DB ring, since every row
+// group reads the same columns.  The 32 x 128 unit is kept for tuning and
+// grouped plans: with 32 rows it ties with the tiled kernel.  Every wave
+// holds seven class accumulators per sub-tile: 112 registers for the four
+// sub-tiles of the 64- and 128-row units, as in the tiled kernel.
 //
 // Operand layout of v_mfma_i32_16x16x64_i8: lane l supplies row (A) or
 // column (B) l % 16 and the 16 bytes of k-group l / 16 of the 64-row chunk;
@@ -48,9 +49,10 @@ constexpr uint32_t QKSUPER = 2048;                  // rows of k per int32 accum
 // buffers per block, RING DB chunks per wave (RING - 1 = PF in flight).
 // SHDB: one DB ring for the block (the row groups share the columns),
 // else one per wave.
-template <int RS_, int WR_, int NQ_, int RING_, bool SHDB_ = false>
+template <int RS_, int WR_, int NQ_, int RING_, bool SHDB_ = false, int RN_ = 1>
 struct QShape {
     static constexpr int RS = RS_;
+    static constexpr int RN = RN_;                       // 16-column sub-tiles per wave
     static constexpr int WR = WR_;
     static constexpr int NQ = NQ_;
     static constexpr int RING = RING_;
@@ -58,7 +60,7 @@ struct QShape {
     static constexpr int PF = RING - 1;
     static constexpr int BM = 16 * RS * WR;              // query rows of a unit
     static constexpr int WC = QWAVES / WR;               // waves per row group
-    static constexpr int BN = 16 * WC;                   // DB columns of a unit
+    static constexpr int BN = 16 * RN * WC;              // DB columns of a unit
     static constexpr int QCH = 4 * BM * QKCH;            // bytes of one query chunk (four digits)
     static constexpr int QL = QCH / 1024 / QWAVES;       // 1 KiB query loads per wave and chunk
     static constexpr int DBS = SHDB ? 4 * BN * QKCH : QWAVES * DBCH;   // bytes of one DB ring slot, all waves
@@ -68,6 +70,7 @@ struct QShape {
     static_assert(DL >= 1 && (!SHDB || DL * QWAVES * 1024 == DBS), "DB chunk loads");
     static_assert(DB_LDS + RING * DBS <= LDS_BYTES, "LDS");
     static_assert(PF >= 1 && (SHDB || (PF <= NQ && PF >= NQ - 1)) && NQ >= 2, "pipeline depths");
+    static_assert(RN == 1 || SHDB, "a wave's own DB ring holds 16 columns");
 };
 
 template <int N>
@@ -134,7 +137,8 @@ __device__ __forceinline__ QUnit decode_unit(uint32_t u, const MfmaJob &J, uint3
 template <class S, int MODE>
 __global__ void __launch_bounds__(64 * QWAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))
 rowsel_mfma_qres_kernel(const MfmaJob J) {
-    constexpr int RS = S::RS, WR = S::WR, BM = S::BM, BN = S::BN, NQ = S::NQ, RING = S::RING, PF = S::PF;
+    constexpr int RS = S::RS, RN = S::RN, WR = S::WR, BM = S::BM, BN = S::BN, NQ = S::NQ, RING = S::RING,
+                  PF = S::PF;
     constexpr int QCH = S::QCH, QL = S::QL, DBL = S::DL, DBS = S::DBS;
     constexpr bool SHDB = S::SHDB;
     __shared__ __attribute__((aligned(1024))) int8_t lds[LDS_BYTES];
@@ -166,7 +170,7 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
     // with the same chunk swizzle as the query (load v of a chunk is 16
     // columns of one digit: v = d * (BN / 16) + cq).
     int8_t *const ring = lds + S::DB_LDS + (SHDB ? 0 : wv * DBCH);
-    const uint32_t bcol = wc * 16 + lane % 16;
+    const uint32_t bcol = wc * 16 * RN + lane % 16;
     const uint32_t b_lane = SHDB ? bcol * QKCH + ((lane / 16) ^ ((bcol >> 1) & 3)) * 16 : lane * 16;
     auto q_base = [&](const QUnit &u) { return J.qd + u.p * 4 * qstride + (uint64_t)u.m0 * QKCH + qlane; };
     // per-lane source of DB load j (columns past D1 are never stored); a
@@ -178,7 +182,7 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
             const uint32_t n = u.n0 + cq * 16 + lane / 4;
             return J.dbd + u.p * 4 * dstride + d * dstride + (uint64_t)min(n, d1 - 1) * QKCH + (qlane % QKCH);
         }
-        const uint32_t n = u.n0 + wc * 16 + lane % 16;
+        const uint32_t n = u.n0 + wc * 16 * RN + lane % 16;
         return J.dbd + u.p * 4 * dstride + (uint64_t)min(n, d1 - 1) * QKCH + (lane / 16) * 16;
     };
     // the unit after iteration i (iteration i's own past the last one)
@@ -246,12 +250,12 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
         d_kc += d_kc < nkc;
     };
 
-    i32x4 acc[7][RS];
+    i32x4 acc[7][RS * RN];
     auto zero_acc = [&]() {
 #pragma unroll
         for (int c = 0; c < 7; ++c)
 #pragma unroll
-            for (int rs = 0; rs < RS; ++rs) acc[c][rs] = (i32x4){0, 0, 0, 0};
+            for (int t = 0; t < RS * RN; ++t) acc[c][t] = (i32x4){0, 0, 0, 0};
     };
     zero_acc();
 
@@ -262,14 +266,14 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
     auto flush = [&](bool first, bool last) {
         const EpiQ mq = J.q[cu.l];
         uint32_t *pt = J.out + (uint64_t)cu.pl * J.mp * J.sstride;
-        const uint32_t n = cu.n0 + wc * 16 + lane % 16;
 #pragma unroll
-        for (int rs = 0; rs < RS; ++rs)
+        for (int t = 0; t < RS * RN; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                const uint32_t rs = t / RN, n = cu.n0 + wc * 16 * RN + (t % RN) * 16 + lane % 16;
                 int gr[7];
 #pragma unroll
-                for (int c = 0; c < 7; ++c) gr[c] = acc[c][rs][r];
+                for (int c = 0; c < 7; ++c) gr[c] = acc[c][t][r];
                 uint32_t v = combine_classes<MODE>(gr, mq);
                 const uint32_t m = cu.m0 + wr * 16 * RS + rs * 16 + 4 * (lane / 16) + r;
                 if (m < J.mp && n < d1) {
@@ -321,9 +325,12 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
         // 4.
         const int8_t *bb = ring + c_slot * DBS + b_lane;
         c_slot = c_slot + 1 == RING ? 0 : c_slot + 1;
-        i32x4 b[4];
+        i32x4 b[4][RN];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) b[d] = *reinterpret_cast<const i32x4 *>(bb + d * (SHDB ? BN * QKCH : 1024));
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int rn = 0; rn < RN; ++rn)
+                b[d][rn] = *reinterpret_cast<const i32x4 *>(bb + d * (SHDB ? BN * QKCH : 1024) + rn * 16 * QKCH);
         // query digit i's RS fragments go to buffer i % 2, two digits ahead
         // of their MFMAs, so each digit's reads overlap the previous digit's
         // MFMAs
@@ -344,8 +351,10 @@ rowsel_mfma_qres_kernel(const MfmaJob J) {
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int rs = 0; rs < RS; ++rs)
-                    acc[i + j][rs] =
-                        __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i % 2][rs], b[j], acc[i + j][rs], 0, 0, 0);
+#pragma unroll
+                    for (int rn = 0; rn < RN; ++rn)
+                        acc[i + j][rs * RN + rn] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            a[i % 2][rs], b[j][rn], acc[i + j][rs * RN + rn], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
             if (i + 2 < 4) {
                 read_a(i + 2);
@@ -389,23 +398,31 @@ int qres_cu_count() {
 
 }  // namespace
 
-// Unit shapes (RS, WR; query buffers, DB ring slots): 32 x 128, 64 x 128,
-// 128 x 64 (one DB ring for the block: per-wave rings, which load each
-// column twice, made the 64-client GEMM 4.28 ms against 4.16).
+// Unit shapes (sub-tiles per wave RS x RN, WR row groups; query buffers, DB
+// ring slots): 32 x 128, 64 x 128, 96 x 64 and 128 x 64, the last two with one
+// DB ring for the block.  Measured on the 512 x 512, N = 4096 DB (GEMM
+// alone): the 128-row unit with 4 x 1 sub-tiles per wave (each wave all 64
+// rows of 16 columns) and per-wave DB rings, which load each column twice,
+// took 4.28 ms for 64 clients, with one shared ring 4.16 ms, and with 2 x 2
+// sub-tiles per wave (a fifth fewer LDS fragment reads) 4.05-4.14 ms against
+// 4.18-4.26 ms on the same boxes; the 96-row unit took 3.15-3.30 ms for 33 to
+// 48 clients, where 128-row units took 3.71-4.18 ms.  A 64 x 128 unit with
+// 2 x 2 sub-tiles and a shared ring tied with the 4 x 1 form.
 struct QVariant {
-    uint32_t rs, wr, nq, ring;
+    uint32_t rs, wr, nq, ring, rn;
     uint32_t rows() const { return 16 * rs * wr; }
-    uint32_t cols() const { return 16 * (QWAVES / wr); }
+    uint32_t cols() const { return 16 * rn * (QWAVES / wr); }
     uint32_t min_chunks() const { return std::max(nq - 1, ring - 1); }
 };
-static const QVariant QRES[] = {{2, 1, 3, 4}, {4, 1, 3, 3}, {4, 2, 2, 3}};
+static const QVariant QRES[] = {{2, 1, 3, 4, 1}, {4, 1, 3, 3, 1}, {3, 2, 3, 3, 1}, {2, 4, 2, 3, 2}};
 constexpr uint32_t NQRES = sizeof(QRES) / sizeof(QRES[0]);
+uint32_t qres_shape_count() { return NQRES; }
 uint32_t qres_min_chunks(uint32_t shape) { return QRES[shape].min_chunks(); }
 
 // PIR_MFMA_KERNEL=qres or tile forces a kernel, else the query-resident one
 // for 64, 96 and 128 rows (measured on the 512 x 512, N = 4096 DB: 64 rows
-// 2.17 ms against 2.43 ms tiled, 96 rows 3.89 against 4.02, 128 rows 4.16
-// against 4.61; with 32 rows the two tie).
+// 2.17 ms against 2.43 ms tiled, 96 rows 3.3 against 4.0, 128 rows 4.1
+// against 4.6; with 32 rows the two tie).
 bool qres_preferred(uint32_t mp, uint32_t nkc) {
     if (nkc < qres_min_chunks(qres_shape_for(mp))) return false;
     if (const char *e = std::getenv("PIR_MFMA_KERNEL")) {
@@ -420,7 +437,7 @@ uint32_t qres_shape_for(uint32_t mp) {
         const int v = std::atoi(e);
         if (v >= 0 && (uint32_t)v < NQRES && QRES[v].rows() >= std::min(mp, 128u)) return (uint32_t)v;
     }
-    return mp <= 32 ? 0u : mp <= 64 ? 1u : 2u;
+    return mp <= 32 ? 0u : mp <= 64 ? 1u : mp <= 96 ? 2u : 3u;
 }
 uint32_t qres_rows(uint32_t shape) { return QRES[shape].rows(); }
 uint32_t qres_cols(uint32_t shape) { return QRES[shape].cols(); }
@@ -462,7 +479,8 @@ void launch_mfma_qres(const MfmaJob &job, hipStream_t st) {
     switch (job.wm) {
         case 0: go_mode(QShape<2, 1, 3, 4>{}); break;
         case 1: go_mode(QShape<4, 1, 3, 3>{}); break;
-        default: go_mode(QShape<4, 2, 2, 3, true>{}); break;
+        case 2: go_mode(QShape<3, 2, 3, 3, true>{}); break;
+        default: go_mode(QShape<2, 4, 2, 3, true, 2>{}); break;
     }
     PIR_LAUNCH_CHECK();
 }

@@ -4,8 +4,9 @@ oracle, word for word, and against the tiled MFMA kernel on the same inputs.
 
 PIR_MFMA_KERNEL=qres forces single pir_rowsel calls on the MFMA path through
 it (PIR_MFMA_KERNEL=tile through the tiled kernel).  The shapes cover its
-three unit shapes (32 x 128 and 64 x 128 with a DB ring per wave, 128 x 64
-with one per block; picked from the padded row count, or forced taller) and more than 128 rows (units in several row blocks), D1 ragged
+four unit shapes (32 x 128 and 64 x 128 with a DB ring per wave, 96 x 64
+and 128 x 64 with one per block; picked from the padded row count, or
+forced taller) and more than 128 rows (units in several row blocks), D1 ragged
 against every unit width, D0 at the fewest chunks of k the kernel takes, D0
 above the 2048-row int32 accumulation (flushes that add to what an earlier
 flush of the unit stored), the split and wide recombination forms, four
@@ -41,12 +42,14 @@ SHAPES = [
     # (64- and 128-row units) chunks of 64 rows of k
     (64, P2, 200, 300, 1),           # 32-row units, 4 chunks, D1 ragged
     (64, P2, 130, 33, 17),           # 64-row units, 3 chunks (the last ragged)
-    (128, P2, 160, 40, 33),          # 96 rows in 128-row units
+    (128, P2, 160, 40, 33),          # 66 rows in 96-row units
     (16, P2, 200, 5, 64),            # 128 rows, D1 = 5
     (64, P2, 300, 100, 80),          # 160 rows: two 128-row blocks
     (16, P2, 4200, 5, 2),            # 66 chunks: flushes at 32, 64, 66
     (16, P2, 2100, 20, 20),          # 64-row units, 33 chunks
     (16, P2, 4100, 8, 50),           # 128-row units, 65 chunks
+    (16, P2, 4100, 70, 40),          # 96-row units, 65 chunks, D1 ragged
+    (64, P2, 256, 200, 48),          # 96 rows, whole units, 4 chunks
     (64, (954376193,), 600, 24, 3),  # split recombination
     (64, (954376193, 1073692673), 130, 40, 17),
     (32, synth.PRIMES_Q108, 130, 33, 9),
@@ -89,7 +92,7 @@ def test_qres_matches_oracle(pir, shape, monkeypatch):
     pir.pir_db_free(db)
 
 
-@pytest.mark.parametrize("B", [8, 30, 64])
+@pytest.mark.parametrize("B", [8, 30, 40, 64])
 def test_qres_all_q_minus_one(pir, B, monkeypatch):
     # every product (q-1)^2 = 1 mod q with the largest digit sums: each output
     # is D0 mod q (D0 above the 2048-row accumulation chunk)
@@ -137,16 +140,17 @@ def test_qres_coefficient_domain_query(pir, monkeypatch):
     pir.pir_db_free(db)
 
 
-FORCED = [(s, 2) for s in SHAPES if 2 * s[4] <= 64] + [((16, P2, 200, 20, 30), 2)] + \
-         [(s, 1) for s in SHAPES if 2 * s[4] <= 32]
+FORCED = [(s, 3) for s in SHAPES if 2 * s[4] <= 64] + [((16, P2, 200, 20, 30), 3)] + \
+         [(s, 2) for s in SHAPES if 2 * s[4] <= 64] + [(s, 1) for s in SHAPES if 2 * s[4] <= 32]
 
 
 @pytest.mark.parametrize("shape,variant", FORCED,
                          ids=[f"N{s[0]}L{len(s[1])}_{s[2]}x{s[3]}_B{s[4]}_u{v}" for s, v in FORCED])
 def test_qres_larger_units(pir, shape, variant, monkeypatch):
     """Rows in units taller than they need (PIR_QRES_VARIANT picks the unit
-    shape): 128-row units, whose two row groups share one DB ring, and 64-row
-    units, with half or more of their rows past the batch."""
+    shape): 128-row units (four row groups of 2 x 2 sub-tiles per wave
+    sharing one DB ring), 96-row units (two row groups, one ring) and 64-row
+    units, with a third or more of their rows past the batch."""
     say("qres larger units", shape, variant)
     monkeypatch.setenv("PIR_QRES_VARIANT", str(variant))
     db, q, want = _case(pir, shape)
