@@ -138,10 +138,11 @@ void pir_db_free(pir_db *db);
  * otherwise); PIR_PATH_AUTO picks, when both layouts exist, the streaming
  * VALU kernel for B <= 2 (B = 1 when a prime is 2^30 or more, where each
  * client is its own pass over the DB) and the INT8 MFMA kernels above.  On
- * the MFMA path 2B rounded up to 32 rows picks the kernel: 64 to 128 rows
- * (17 to 64 clients, with D0 above 64) the query-resident
- * one, else the tiled one; PIR_MFMA_KERNEL=qres or =tile in the environment
- * forces one (tuning and tests; the results are the same bit for bit). */
+ * the MFMA path 2B rounded up to 32 rows picks the kernel: from 64 rows up
+ * (17 clients and more, with D0 above 64) the query-resident one (units of
+ * 64, 96 or 128 rows), else the tiled one; PIR_MFMA_KERNEL=qres or =tile in
+ * the environment forces one (tuning and tests; the results are the same
+ * bit for bit). */
 pir_status pir_rowsel(const pir_db *db, const uint32_t *q_dev, uint32_t B,
                       uint32_t *out_dev, pir_path path, void *hip_stream);
 

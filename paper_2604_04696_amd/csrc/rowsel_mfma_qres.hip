@@ -1,5 +1,5 @@
-// RowSel on the INT8 matrix cores, query-resident form, for 64 to 128 query
-// rows (2B = 33..64; more rows run in blocks of the unit's height).
+// RowSel on the INT8 matrix cores, query-resident form, for 64 query rows
+// and more (2B >= 33; above 128 rows in blocks of the unit's height).
 //
 // The arithmetic is that of rowsel_mfma.hip (four balanced signed digits per
 // residue, sixteen digit products summed per weight class s = i + j in int32,
@@ -420,24 +420,32 @@ uint32_t qres_shape_count() { return NQRES; }
 uint32_t qres_min_chunks(uint32_t shape) { return QRES[shape].min_chunks(); }
 
 // PIR_MFMA_KERNEL=qres or tile forces a kernel, else the query-resident one
-// for 64, 96 and 128 rows (measured on the 512 x 512, N = 4096 DB: 64 rows
-// 2.17 ms against 2.43 ms tiled, 96 rows 3.3 against 4.0, 128 rows 4.1
-// against 4.6; with 32 rows the two tie).
+// from 64 rows up (measured on the 512 x 512, N = 4096 DB: 64 rows 2.17 ms
+// against 2.43 ms tiled, 96 rows 3.3 against 4.0, 128 rows 4.1 against 4.6;
+// with 32 rows the two tie).
 bool qres_preferred(uint32_t mp, uint32_t nkc) {
     if (nkc < qres_min_chunks(qres_shape_for(mp))) return false;
     if (const char *e = std::getenv("PIR_MFMA_KERNEL")) {
         if (!std::strcmp(e, "qres")) return true;
         if (!std::strcmp(e, "tile")) return false;
     }
-    return mp >= 64 && mp <= 128;
+    return mp >= 64;
 }
 
+// The unit for mp rows: the one of mp's height up to 128 rows; above, the
+// 64-, 96- or 128-row unit with the fewest rows computed (the taller one on
+// a tie: the GEMM's time per computed row is about the same for the three).
 uint32_t qres_shape_for(uint32_t mp) {
     if (const char *e = std::getenv("PIR_QRES_VARIANT")) {   // tuning runs
         const int v = std::atoi(e);
         if (v >= 0 && (uint32_t)v < NQRES && QRES[v].rows() >= std::min(mp, 128u)) return (uint32_t)v;
     }
-    return mp <= 32 ? 0u : mp <= 64 ? 1u : mp <= 96 ? 2u : 3u;
+    if (mp <= 128) return mp <= 32 ? 0u : mp <= 64 ? 1u : mp <= 96 ? 2u : 3u;
+    auto computed = [&](uint32_t s2) { return (mp + QRES[s2].rows() - 1) / QRES[s2].rows() * QRES[s2].rows(); };
+    uint32_t best = 3;
+    for (uint32_t s2 : {2u, 1u})
+        if (computed(s2) < computed(best)) best = s2;
+    return best;
 }
 uint32_t qres_rows(uint32_t shape) { return QRES[shape].rows(); }
 uint32_t qres_cols(uint32_t shape) { return QRES[shape].cols(); }
