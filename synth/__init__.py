@@ -270,10 +270,11 @@ PAPER_Q108 = Workload("rowsel_n4096_l4q108_256x512_b32", 6, 4096, PRIMES_Q108, 2
 # Offered loads of the serving workload, frozen: Poisson rates of 0.7x and
 # 0.9x the saturated rate (twice the 256-client admission cap arriving at
 # once, after an untimed warm-up burst) measured on one MI355X with this
-# library, 3100 queries/s (3095 and 3104 in two runs).  An earlier
-# calibration, 2480 queries/s, had no warm-up: its saturated run paid the
-# step kernels' first launches.
-SERVE_SATURATED_QPS = 3100.0
+# library, 3490 queries/s (3482-3503 in four runs).  Earlier calibrations:
+# 2480 queries/s without the warm-up (the saturated run paid the step
+# kernels' first launches), then 3100 queries/s before steps with more than
+# 64 clients moved to the query-resident kernel.
+SERVE_SATURATED_QPS = 3490.0
 SERVE_LOADS = (0.7, 0.9)
 SERVE_RATES_QPS = tuple(round(f * SERVE_SATURATED_QPS, 1) for f in SERVE_LOADS)
 
