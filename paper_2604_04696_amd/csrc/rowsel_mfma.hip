@@ -572,33 +572,37 @@ rowsel_mfma_persistent(const MfmaJob one, const MfmaJob *__restrict__ jobs, uint
 
 // Output transpose: staging [P][mp][ss] (P = L*N points, ss = d1 rounded up
 // to a multiple of 4) -> boundary layout [B][2][d1][L][N], i.e. for every row
-// m < m_rows a P x d1 -> d1 x P transpose.  A block takes one row m, 64
-// points and 64 columns: it reads 64 runs of 256 bytes (columns contiguous)
-// and writes 64 runs of 256 bytes (points contiguous), 16-byte vectors on
+// m < m_rows a P x d1 -> d1 x P transpose.  A block takes one row m, TP
+// points and TC columns: it reads TP runs of 4 TC bytes (columns contiguous)
+// and writes TC runs of 4 TP bytes (points contiguous), 16-byte vectors on
 // both sides through a padded LDS tile (the paper's output transposition of
 // sec. 5.2.2, here one coalesced pass).  P is a multiple of 4 (N >= 4).
+template <int TP, int TC>
 __global__ void __launch_bounds__(256)
 out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ out, uint32_t mp, uint32_t d1,
                      uint32_t ss, uint32_t P, uint32_t nblk_n, uint32_t nblk_p) {
-    __shared__ __attribute__((aligned(16))) uint32_t tile[64][68];   // [column][point]
+    __shared__ __attribute__((aligned(16))) uint32_t tile[TC][TP + 4];   // [column][point]
+    constexpr int NQ = TC / 4, PQ = TP / 4;                               // column and point quads
+    constexpr int LOADS = TP * NQ / 256, STORES = TC * PQ / 256;
+    static_assert(LOADS * 256 == TP * NQ && STORES * 256 == TC * PQ, "tile divides among the threads");
     const uint32_t tid = threadIdx.x;
     uint32_t b = blockIdx.x;
     const uint32_t pb = b % nblk_p;
     b /= nblk_p;
     const uint32_t nb = b % nblk_n;
     const uint32_t m = b / nblk_n;
-    const uint32_t p0 = pb * 64, n0 = nb * 64;
-    uint4 v[4];
+    const uint32_t p0 = pb * TP, n0 = nb * TC;
+    uint4 v[LOADS];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+    for (int j = 0; j < LOADS; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / NQ, nq = e % NQ;
         v[j] = p0 + pi < P && n0 + 4 * nq < d1
                    ? ld_nt(reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq))
                    : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+    for (int j = 0; j < LOADS; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / NQ, nq = e % NQ;
         tile[4 * nq + 0][pi] = v[j].x;
         tile[4 * nq + 1][pi] = v[j].y;
         tile[4 * nq + 2][pi] = v[j].z;
@@ -606,22 +610,27 @@ out_transpose_kernel(const uint32_t *__restrict__ stage, uint32_t *__restrict__ 
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t e = tid + 256 * j, ni = e / 16, pq = e % 16;
+    for (int j = 0; j < STORES; ++j) {
+        const uint32_t e = tid + 256 * j, ni = e / PQ, pq = e % PQ;
         if (n0 + ni < d1 && p0 + 4 * pq < P)
             st_nt(reinterpret_cast<uint4 *>(out + ((uint64_t)m * d1 + n0 + ni) * P + p0 + 4 * pq),
                   *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]));
     }
 }
 
+// Points and columns per transpose block: 512-byte write runs.  Measured on
+// the 64-client output (2 GiB each way): 128 x 64 0.67 ms, 256 x 32 0.68 ms,
+// 64 x 64 0.74-0.79 ms, 64 x 128 0.78 ms, 128 x 128 (68 KiB of LDS) 0.95 ms.
+constexpr int OT_P = 128, OT_C = 64;
+
 void launch_out_transpose(const uint32_t *stage, uint32_t *out, uint32_t m_rows, uint32_t mp, uint32_t d1,
                           uint32_t slots, hipStream_t st) {
-    const uint32_t nblk_n = (d1 + 63) / 64, nblk_p = (slots + 63) / 64;
+    const uint32_t nblk_n = (d1 + OT_C - 1) / OT_C, nblk_p = (slots + OT_P - 1) / OT_P;
     const uint64_t blocks = (uint64_t)m_rows * nblk_n * nblk_p;
     if (!blocks) return;
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "transpose launch too large");
-    out_transpose_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, out, mp, d1, staging_stride(d1), slots, nblk_n,
-                                                           nblk_p);
+    out_transpose_kernel<OT_P, OT_C><<<(uint32_t)blocks, 256, 0, st>>>(stage, out, mp, d1, staging_stride(d1),
+                                                                       slots, nblk_n, nblk_p);
     PIR_LAUNCH_CHECK();
 }
 
