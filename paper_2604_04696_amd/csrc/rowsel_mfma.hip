@@ -74,8 +74,10 @@ struct DigitCenter {
 };
 
 constexpr uint32_t DP_ROWS = 4;                         // rows per block
-constexpr uint32_t DP_THREADS = 128 * DP_ROWS;
-constexpr uint32_t DP_ROW = 64 * 256 + 256 / DP_ROWS;   // LDS bytes per row of the block (64 points x 256 + offset)
+constexpr uint32_t DP_PTS = 64;                         // points per block
+constexpr uint32_t DP_PQ = DP_PTS / 4;                  // four-point groups per block
+constexpr uint32_t DP_THREADS = DP_PQ * 8 * DP_ROWS;    // a thread: four points x eight k of one row
+constexpr uint32_t DP_ROW = DP_PTS * 256 + 64;          // LDS bytes per row of the block (+ offset)
 
 // LDS byte offset of the 16-byte piece kq (k = 16 kq .. 16 kq + 15) of
 // digit d of point pp in row rr.
@@ -92,16 +94,16 @@ digit_planes_kernel(const uint32_t *__restrict__ src, uint64_t s_r, uint64_t s_k
     __shared__ __attribute__((aligned(16))) uint8_t tile[DP_ROWS * DP_ROW];
     const uint32_t tid = threadIdx.x;
     uint64_t b = blockIdx.x;
-    const uint32_t npb = (P + 63) / 64;
+    const uint32_t npb = (P + DP_PTS - 1) / DP_PTS;
     const uint32_t pb = (uint32_t)(b % npb);
     b /= npb;
     const uint32_t kb = kblk0 + (uint32_t)(b % nkblk);
     const uint32_t r0 = DP_ROWS * (uint32_t)(b / nkblk);
-    const uint32_t k0 = kb * 64, p0 = pb * 64;
+    const uint32_t k0 = kb * 64, p0 = pb * DP_PTS;
 
     // thread: points p0 + 4 pq .. + 3, k0 + 8 kg .. + 7, row r0 + rr; all
     // loads are issued before the first digit split
-    const uint32_t pq = tid % 16, kg = (tid / 16) % 8, rr = tid / 128;
+    const uint32_t pq = tid % DP_PQ, kg = (tid / DP_PQ) % 8, rr = tid / (DP_PQ * 8);
     const uint32_t r = r0 + rr, pb4 = p0 + 4 * pq;
     uint4 v[8];
 #pragma unroll
@@ -187,7 +189,7 @@ static void launch_digit_planes(const pir_db &db, const uint32_t *src, uint64_t 
     // the padding up to Kp (Kp is D0 rounded up to 64)
     const uint32_t kb0 = klo / 64, kb1 = (khi + 63) / 64;
     const uint32_t nkb = kb1 - kb0;
-    const uint64_t blocks = (uint64_t)((P + 63) / 64) * nkb * ((R + DP_ROWS - 1) / DP_ROWS);
+    const uint64_t blocks = (uint64_t)((P + DP_PTS - 1) / DP_PTS) * nkb * ((R + DP_ROWS - 1) / DP_ROWS);
     if (blocks >= (1ull << 31)) PIR_FAIL(PIR_EINVAL, "digit-plane launch too large");
     DigitCenter dc{};
     for (uint32_t l = 0; l < db.p.nprimes; ++l) dc.q[l] = db.p.q[l];
