@@ -26,14 +26,19 @@ namespace pir {
 // Staging [cp][mp][ss] of one step (cp points, starting at point p_begin of
 // the DB; ss = d1 rounded up to a multiple of 4) -> per-row destinations.
 // Row m holds slot m/2, component m%2; row_dst[m] is that component's
-// [D1][L*N] array (0 = discard).  A block takes one row, 64 columns and 64
-// points and moves 256-byte runs of 16-byte vectors on both sides through a
-// padded LDS tile (cp, p_begin and pall are multiples of 4).
+// [D1][L*N] array (0 = discard).  A block takes one row, SC_C columns and
+// SC_P points and moves 16-byte vectors through a padded LDS tile: 256-byte
+// read runs and 512-byte write runs (the shape the output transpose of
+// single calls measured fastest; cp, p_begin and pall are multiples of 4).
+constexpr int SC_P = 128, SC_C = 64;
+
 __global__ void __launch_bounds__(256)
 serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restrict__ row_dst, uint32_t mp,
                      uint32_t d1, uint32_t ss, uint32_t cp, uint32_t p_begin, uint32_t pall, uint32_t nblk_n,
                      uint32_t nblk_p) {
-    __shared__ __attribute__((aligned(16))) uint32_t tile[64][68];   // [column][point]
+    __shared__ __attribute__((aligned(16))) uint32_t tile[SC_C][SC_P + 4];   // [column][point]
+    constexpr int NQ = SC_C / 4, PQ = SC_P / 4, LOADS = SC_P * NQ / 256, STORES = SC_C * PQ / 256;
+    static_assert(LOADS * 256 == SC_P * NQ && STORES * 256 == SC_C * PQ, "tile divides among the threads");
     const uint32_t tid = threadIdx.x;
     uint32_t b = blockIdx.x;
     const uint32_t pb = b % nblk_p;
@@ -42,18 +47,18 @@ serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restr
     const uint32_t m = b / nblk_n;
     uint32_t *dst = reinterpret_cast<uint32_t *>(row_dst[m]);
     if (!dst) return;   // uniform for the block
-    const uint32_t p0 = pb * 64, n0 = nb * 64;
-    uint4 v[4];
+    const uint32_t p0 = pb * SC_P, n0 = nb * SC_C;
+    uint4 v[LOADS];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+    for (int j = 0; j < LOADS; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / NQ, nq = e % NQ;
         v[j] = p0 + pi < cp && n0 + 4 * nq < d1
                    ? ld_nt(reinterpret_cast<const uint4 *>(stage + ((uint64_t)(p0 + pi) * mp + m) * ss + n0 + 4 * nq))
                    : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t e = tid + 256 * j, pi = e / 16, nq = e % 16;
+    for (int j = 0; j < LOADS; ++j) {
+        const uint32_t e = tid + 256 * j, pi = e / NQ, nq = e % NQ;
         tile[4 * nq + 0][pi] = v[j].x;
         tile[4 * nq + 1][pi] = v[j].y;
         tile[4 * nq + 2][pi] = v[j].z;
@@ -61,8 +66,8 @@ serve_scatter_kernel(const uint32_t *__restrict__ stage, const uint64_t *__restr
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t e = tid + 256 * j, ni = e / 16, pq = e % 16;
+    for (int j = 0; j < STORES; ++j) {
+        const uint32_t e = tid + 256 * j, ni = e / PQ, pq = e % PQ;
         if (n0 + ni < d1 && p0 + 4 * pq < cp)
             st_nt(reinterpret_cast<uint4 *>(dst + (uint64_t)(n0 + ni) * pall + p_begin + p0 + 4 * pq),
                   *reinterpret_cast<const uint4 *>(&tile[ni][4 * pq]));
@@ -241,7 +246,7 @@ struct pir_server {
             KernelTimer::Scope timed(st);
             launch_mfma_grouped(job, nullptr, 1, job.tiles, job.split, deep, st);
         }
-        const uint32_t cp = 4 * ng, nblk_n = (db->p.d1 + 63) / 64, nblk_p = (cp + 63) / 64;
+        const uint32_t cp = 4 * ng, nblk_n = (db->p.d1 + SC_C - 1) / SC_C, nblk_p = (cp + SC_P - 1) / SC_P;
         const uint64_t blocks = (uint64_t)rows * nblk_n * nblk_p;
         PIR_REQUIRE(blocks < (1ull << 31), "scatter launch too large");
         serve_scatter_kernel<<<(uint32_t)blocks, 256, 0, st>>>(stage, row_dst_dev, job.mp, db->p.d1, job.sstride,
