@@ -52,7 +52,7 @@ typedef enum {
     PIR_ENOMEM = -2,        /* device allocation failed */
     PIR_EDEVICE = -3,       /* a HIP runtime call failed */
     PIR_EBUSY = -4,         /* serving: request not admitted now (capacity) */
-    PIR_EUNSUPPORTED = -5   /* valid request this build does not implement */
+    PIR_EUNSUPPORTED = -5   /* valid request this library does not implement */
 } pir_status;
 
 #define PIR_MAX_PRIMES 4
