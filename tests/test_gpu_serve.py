@@ -1,7 +1,9 @@
 """GPU tests of the continuous-batching server: every completed request's
-output equals the oracle's RowSel of its query, a request gives the same
-bits alone and in a mix, requests arriving while others run are admitted,
-malformed requests fail alone, and the HBM budget bounds the capacity."""
+output equals the oracle's RowSel of its query (also with steps whose
+active rows reach every step kernel, up to 80 clients at once), a request
+gives the same bits alone and in a mix, requests arriving while others run
+are admitted, malformed requests fail alone, and the HBM budget bounds the
+capacity."""
 import time
 
 import numpy as np
@@ -121,6 +123,35 @@ def test_serve_budget_bounds_capacity(pir, served):
     pir.pir_server_destroy(small)
     with pytest.raises(pir.PirError, match="holds no client"):
         pir.pir_server_create(db, max_clients=4, hbm_budget=1024)
+
+
+def test_serve_many_clients_every_kernel(pir):
+    """Steps whose active rows span the step kernels: up to 16 clients (tiled
+    32-row shape), 17-32 (64-row query-resident units), 33-48 (96-row),
+    49-64 (128-row) and more than 64 (query-resident row blocks), on a DB
+    whose K spans four 64-row chunks; 150 requests arrive in waves and every
+    output word is compared with the oracle."""
+    n, primes, d0, d1 = 16, PR, 200, 40
+    coeffs = synth.db_coeffs(82, d0, d1, 2, n)
+    dhat = oracle.ntt_db(coeffs, primes)
+    db = pir.pir_db_create(pir.make_params(n, primes, d0, d1), pir.PIR_LAYOUT_MFMA)
+    pir.pir_db_load_ntt(db, to_dev(dhat), domain=pir.PIR_DOMAIN_NTT)
+    count = 150
+    queries = synth.query_uniform(83, count, d0, primes, n)
+    wants = oracle.rowsel(queries, dhat, primes)
+    qs = [to_dev(queries[i]) for i in range(count)]
+    outs = [empty_u32(2 * d1 * 2 * n) for _ in range(count)]
+    srv = pir.pir_server_create(db, max_clients=160, chunks=2)
+    waves = [(0, 10), (10, 30), (30, 70), (70, 150)]   # the last 80 arrive at once
+    schedule = {2 * t: [(i, qs[i], outs[i]) for i in range(a, b)] for t, (a, b) in enumerate(waves)}
+    got = run_until(pir, srv, schedule, count)
+    torch.cuda.synchronize()
+    assert all(got[i].status == 0 for i in range(count))
+    for i in range(count):
+        g = np_u32(outs[i]).reshape(wants[i].shape)
+        assert np.array_equal(g, wants[i]), f"request {i}: {(g != wants[i]).sum()} words differ"
+    pir.pir_server_destroy(srv)
+    pir.pir_db_free(db)
 
 
 @pytest.mark.timeout(900)
