@@ -225,17 +225,19 @@ coltor_dcp_reg_kernel(const uint32_t *__restrict__ ct, uint32_t ncols, uint32_t 
     // difference; point j goes to position bitrev(j)
 #pragma unroll
     for (int r = 0; r < QR; ++r) {
+        // t < T = 2^(LOGN-4): t and r T are disjoint bit fields (see qf_rpart)
         const uint32_t j = t + r * T;
-        poly[qf_pad(__brev(j) >> (32 - LOGN))] = sub_mod(c1[j], c0[j], q);
+        poly[qf_pad(__brev(t) >> (32 - LOGN)) + qf_pad(__brev((uint32_t)r * T) >> (32 - LOGN))] =
+            sub_mod(c1[j], c0[j], q);
     }
     __syncthreads();
     uint32_t v[QR];
 #pragma unroll
-    for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(t * QR + r)];
+    for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(t * QR) + r];
     intt_reg_block<LOGN, WIDE>(v, t, poly, pr.inv[l], pr.inv[l] + n, q);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, r, LOGN - 4))] = v[r];
+    for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, 0, LOGN - 4)) + qf_pad(qf_rpart(r, LOGN - 4))] = v[r];
     __syncthreads();
     int32_t *dst = digits + ((uint64_t)node * 2 + p) * ell * n;
     for (uint32_t j = tid; j < n; j += L * T) {
@@ -379,7 +381,7 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
             uint32_t v[QR];
 #pragma unroll
             for (int r = 0; r < QR; ++r) {
-                const int32_t d = dg[qf_elem(t, r, LOGN - 4)];
+                const int32_t d = dg[qf_elem(t, 0, LOGN - 4) + qf_rpart(r, LOGN - 4)];
                 v[r] = d < 0 ? (uint32_t)(d + (int64_t)q) : (uint32_t)d;
             }
             ntt_reg_block<LOGN, MODE>(v, t, s, tw, tws, q);
@@ -413,13 +415,13 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
             const uint32_t res = MODE == NTT_WIDE ? reduce_wide(acc[c][r], wraps[c][r], m) : reduce64(acc[c][r], m);
-            s[qf_pad(__brev(t * QR + r) >> (32 - LOGN))] = res;
+            s[qf_pad(__brev(t * QR) >> (32 - LOGN)) + qf_pad(__brev((uint32_t)r) >> (32 - LOGN))] = res;
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
             const uint32_t j = t + r * T;
-            o[c * c_out + j] = add_mod_w(c0[c * c_in + j], s[qf_pad(j)], q);
+            o[c * c_out + j] = add_mod_w(c0[c * c_in + j], s[qf_pad(t) + qf_pad(r * T)], q);
         }
     }
 }

@@ -128,7 +128,7 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
         const uint32_t r1 = pr.r1[l];
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
-            const uint32_t x = q[off + qf_elem(t, r, lo)];
+            const uint32_t x = q[off + qf_elem(t, 0, lo) + qf_rpart(r, lo)];
             if (WIDE) {   // q >= 2^30: [0, 2q) needs 64 bits; reduce fully (no lazy range)
                 const uint64_t y = (uint64_t)x - (uint64_t)__umulhi(x, r1) * qv;
                 v[r] = (uint32_t)(y >= qv ? y - qv : y);
@@ -143,26 +143,28 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
         const uint32_t rlo = (uint32_t)clo;          // registers cover bits [rlo, rlo + 4)
         if (rlo != lo) {                              // redistribute through LDS
             __syncthreads();
+            const uint32_t pw = qf_pad(qf_elem(t, 0, lo)), pr = qf_pad(qf_elem(t, 0, rlo));
             if (live) {
 #pragma unroll
-                for (int r = 0; r < QR; ++r) poly[qf_pad(qf_elem(t, r, lo))] = v[r];
+                for (int r = 0; r < QR; ++r) poly[pw + qf_pad(qf_rpart(r, lo))] = v[r];
             }
             __syncthreads();
             if (live) {
 #pragma unroll
-                for (int r = 0; r < QR; ++r) v[r] = poly[qf_pad(qf_elem(t, r, rlo))];
+                for (int r = 0; r < QR; ++r) v[r] = poly[pr + qf_pad(qf_rpart(r, rlo))];
             }
             lo = rlo;
         }
         if (live) {
+            const uint32_t eb = qf_elem(t, 0, lo);
 #pragma unroll
             for (int x = hi - 1; x >= clo; --x) {
                 const uint32_t bit = 1u << (x - (int)lo), mgroups = n >> (x + 1);
+                const uint32_t gb = mgroups + (eb >> (x + 1));
 #pragma unroll
                 for (int r = 0; r < QR; ++r) {
                     if (r & bit) continue;
-                    const uint32_t e = qf_elem(t, r, lo);
-                    const uint32_t gi = mgroups + (e >> (x + 1));
+                    const uint32_t gi = gb + (qf_rpart(r, lo) >> (x + 1));
                     if (WIDE) {   // canonical butterflies with 64-bit intermediates
                         const uint32_t u = v[r], w = mul_shoup_w(v[r | bit], tw[gi], tws[gi], qv);
                         v[r] = add_mod_w(u, w, qv);
@@ -178,14 +180,15 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
     // store coalesced
     __syncthreads();
     if (live) {
+        const uint32_t pb = qf_pad(__brev(qf_elem(t, 0, lo)) >> (32 - logn));
 #pragma unroll
         for (int r = 0; r < QR; ++r)
-            poly[qf_pad(__brev(qf_elem(t, r, lo)) >> (32 - logn))] = WIDE ? v[r] : qf_reduce4(v[r], qv, 2 * qv);
+            poly[pb + qf_pad(__brev(qf_rpart(r, lo)) >> (32 - logn))] = WIDE ? v[r] : qf_reduce4(v[r], qv, 2 * qv);
     }
     __syncthreads();
     if (live) {
 #pragma unroll
-        for (int r = 0; r < QR; ++r) qn[off + t + r * T] = poly[qf_pad(t + r * T)];
+        for (int r = 0; r < QR; ++r) qn[off + t + r * T] = poly[qf_pad(t) + qf_pad(r * T)];   // t < T = 2^k
     }
 }
 
