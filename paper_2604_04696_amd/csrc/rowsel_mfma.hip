@@ -48,20 +48,22 @@ struct ModQ4m {
 // src[r*s_r + (k - klo)*s_k + p] (points p contiguous) goes to byte k%64 of
 // row r of chunk k/64 of plane [p][d]:
 //   dst[(((p*4 + d)*Kp/64 + k/64)*RS + row0 + r)*64 + k%64].
-// A block (512 threads) takes four rows r .. r+3, 64 k (aligned) and 64
+// A block (1024 threads) takes four rows r .. r+3, 64 k (aligned) and 128
 // points.  A thread loads four consecutive points for eight consecutive k
 // (16-byte loads when the source allows them, else four words), splits each
 // residue into its four digit bytes and transposes bytes in registers
 // (v_perm_b32), so that it holds, per point and digit, the eight bytes of
 // its eight k: one 8-byte LDS store each.  The block then writes one
 // 256-byte run (the four rows' 64-byte chunk rows, adjacent in dst) per
-// point and digit, read from LDS in 16-byte pieces.  LDS (64 KiB) holds
+// point and digit, read from LDS in 16-byte pieces; its reads are 512-byte
+// runs (128 points of one row and k).  LDS (128 KiB) holds
 // [row][point][digit][64 k bytes] with the digit's 64-byte row and the
 // 16-byte piece inside it XOR-swizzled by the point (conflict-free 8-byte
 // stores and 16-byte reads) and row rr's part offset by 64 rr more bytes.
-// (Measured on the 2 GiB query of 64 clients: 0.78 ms; the same with two
-// rows per block 0.82 ms; the form before it, a 4-byte load and 16 4-byte
-// LDS reads per 16 bytes of output, 0.85-0.88 ms.)  k outside [klo, khi) and rows
+// (Measured on the 2 GiB query of 64 clients: 0.75-0.77 ms; 64 points per
+// block 0.78-0.83 ms; two rows per block 0.82 ms; the form before it, a
+// 4-byte load and 16 4-byte LDS reads per 16 bytes of output, 0.85-0.88
+// ms.)  k outside [klo, khi) and rows
 // r >= r_valid read as zero; rows r >= R are not written; 16-byte pieces
 // that straddle [klo, khi) (only when loading a DB in row ranges) are
 // written byte by byte so neighbouring ranges are not overwritten.  CENTER
@@ -74,7 +76,7 @@ struct DigitCenter {
 };
 
 constexpr uint32_t DP_ROWS = 4;                         // rows per block
-constexpr uint32_t DP_PTS = 64;                         // points per block
+constexpr uint32_t DP_PTS = 128;                        // points per block
 constexpr uint32_t DP_PQ = DP_PTS / 4;                  // four-point groups per block
 constexpr uint32_t DP_THREADS = DP_PQ * 8 * DP_ROWS;    // a thread: four points x eight k of one row
 constexpr uint32_t DP_ROW = DP_PTS * 256 + 64;          // LDS bytes per row of the block (+ offset)
