@@ -346,7 +346,11 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
                       const int32_t *__restrict__ digits, uint32_t *__restrict__ out, uint32_t ncols,
                       uint32_t nout, uint32_t L, uint32_t ell, ColtorPrimes pr) {
     constexpr uint32_t n = 1u << LOGN, T = n / QR;
-    extern __shared__ uint32_t s[];                  // n + n/16 words
+    // up to N = 4096 the twiddles are staged in LDS: kept in registers across
+    // the 2 ell transforms they took ~90 VGPRs (236 in all, two waves per
+    // SIMD, 61% of the VALU issue slots used)
+    constexpr bool TW_LDS = LOGN <= 12;
+    extern __shared__ uint32_t s[];                  // n + n/16 words, then (TW_LDS) n twiddle pairs
     const uint32_t t = threadIdx.x;
     // the L limb blocks of a node, and consecutive nodes of a client, run on
     // one XCD: the node's digits and the client's RGSW rows stay in its L2
@@ -368,6 +372,11 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
     }
     const ModQ &m = pr.mod[l];
     const uint32_t *tw = pr.fwd[l], *tws = tw + n;
+    uint2 *stw = reinterpret_cast<uint2 *>(s + n + n / 16);
+    if constexpr (TW_LDS) {
+        tw_pairs_fill<LOGN>(stw, tw, tws, t);
+        __syncthreads();
+    }
     uint64_t acc[2][QR];
     uint32_t wraps[2][QR];
 #pragma unroll
@@ -375,34 +384,44 @@ coltor_mac_reg_kernel(const uint32_t *__restrict__ ct, const uint32_t *__restric
 #pragma unroll
         for (int r = 0; r < QR; ++r) acc[c][r] = 0, wraps[c][r] = 0;
 
-    for (uint32_t p = 0; p < 2; ++p) {
-        for (uint32_t i = 0; i < ell; ++i) {
-            const int32_t *dg = digits + (((uint64_t)node * 2 + p) * ell + i) * n;
-            uint32_t v[QR];
+    // the 2 ell digit polynomials of the node (p, i) in turn; the next one's
+    // values are loaded while the current one is transformed (waiting for
+    // them right before each transform left the SIMDs idle for a third of
+    // the kernel)
+    const uint32_t ne = 2 * ell;
+    const int32_t *dg = digits + (uint64_t)node * ne * n + qf_elem(t, 0, LOGN - 4);
+    int32_t dn[QR];
 #pragma unroll
-            for (int r = 0; r < QR; ++r) {
-                const int32_t d = dg[qf_elem(t, 0, LOGN - 4) + qf_rpart(r, LOGN - 4)];
-                v[r] = d < 0 ? (uint32_t)(d + (int64_t)q) : (uint32_t)d;
-            }
-            ntt_reg_block<LOGN, MODE>(v, t, s, tw, tws, q);
-            const uint4 *row = reinterpret_cast<const uint4 *>(
-                rgsw_p + ((((uint64_t)b * 2 + p) * ell + i) * 2) * LN + (uint64_t)l * n + (uint64_t)t * QR);
+    for (int r = 0; r < QR; ++r) dn[r] = dg[qf_rpart(r, LOGN - 4)];
+    for (uint32_t pi = 0; pi < ne; ++pi) {
+        const uint32_t p = pi >= ell, i = pi - p * ell;
+        uint32_t v[QR];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
+        for (int r = 0; r < QR; ++r) v[r] = dn[r] < 0 ? (uint32_t)(dn[r] + (int64_t)q) : (uint32_t)dn[r];
+        if (pi + 1 < ne) {
+            dg += n;
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const uint4 w4 = row[c * (LN / 4) + g];
-                    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+            for (int r = 0; r < QR; ++r) dn[r] = dg[qf_rpart(r, LOGN - 4)];
+        }
+        if constexpr (TW_LDS) ntt_reg_block<LOGN, MODE>(v, t, s, TwPairsLds<LOGN>{stw}, q);
+        else ntt_reg_block<LOGN, MODE>(v, t, s, TwGlobal{tw, tws}, q);
+        const uint4 *row = reinterpret_cast<const uint4 *>(
+            rgsw_p + ((((uint64_t)b * 2 + p) * ell + i) * 2) * LN + (uint64_t)l * n + (uint64_t)t * QR);
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int r = 4 * g + k;
-                        // NTT_GROW: the unreduced value (below (1 + 2 logN) q)
-                        // goes into the 64-bit sum; the host checks 2 ell of
-                        // these products fit
-                        const uint32_t x = MODE == NTT_LAZY ? qf_reduce4(v[r], q, 2 * q) : v[r];
-                        if (MODE == NTT_WIDE) mad_wide(acc[c][r], wraps[c][r], x, w[k]);
-                        else acc[c][r] += (uint64_t)x * w[k];
-                    }
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const uint4 w4 = row[c * (LN / 4) + g];
+                const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int r = 4 * g + k;
+                    // NTT_GROW: the unreduced value (below (1 + 2 logN) q)
+                    // goes into the 64-bit sum; the host checks 2 ell of
+                    // these products fit
+                    const uint32_t x = MODE == NTT_LAZY ? qf_reduce4(v[r], q, 2 * q) : v[r];
+                    if (MODE == NTT_WIDE) mad_wide(acc[c][r], wraps[c][r], x, w[k]);
+                    else acc[c][r] += (uint64_t)x * w[k];
                 }
             }
         }
@@ -532,7 +551,7 @@ void launch_coltor_stage(const pir_params &ring, const uint32_t *ct, uint32_t B,
         rgsw_permute_kernel<<<(uint32_t)((rg_words + 255) / 256), 256, 0, st>>>(rgsw, rgp.as<uint32_t>(),
                                                                              rg_words, logn);
         PIR_LAUNCH_CHECK();
-        const size_t lds = (size_t)(n + n / 16) * sizeof(uint32_t);
+        const size_t lds = (size_t)(n + n / 16) * sizeof(uint32_t) + (logn <= 12 ? (size_t)n * sizeof(uint2) : 0);
         auto go2 = [&](auto kern) {
             PIR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

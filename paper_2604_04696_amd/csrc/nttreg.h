@@ -65,6 +65,47 @@ enum : int {
     NTT_GROW = 2,   // (1 + 2 logN) q < 2^32: no correction at all, (x + t, x - t + 2q)
 };
 
+// Twiddle sources of ntt_reg_block: tw(x, gi) returns the psi power of group
+// index gi (used by stage x) and its Shoup companion.
+struct TwGlobal {   // two tables in global memory
+    const uint32_t *w, *ws;
+    __device__ __forceinline__ uint2 operator()(int, uint32_t gi) const { return make_uint2(w[gi], ws[gi]); }
+};
+
+// {w, w'} pairs staged in LDS (tw_pairs_fill).  Stage x uses the groups
+// [N >> (x+1), N >> x); in the last chunk (register bits from 0, element
+// r | 16t) thread t needs groups (N >> (x+1)) + t K + k, k < K = 2^(3-x), of
+// stages x <= 3.  Those are stored at (N >> (x+1)) + k N/16 + t, so that the
+// lanes of a wave read consecutive pairs instead of pairs K apart (K-way bank
+// conflicts); the slot of a group depends on the group alone, so other
+// chunks' reads of these stages stay correct.
+template <int LOGN>
+__device__ __forceinline__ uint32_t tw_pair_slot(int x, uint32_t gi) {
+    constexpr uint32_t n = 1u << LOGN, T = n / QR;
+    if (x > 3) return gi;
+    const uint32_t base = n >> (x + 1), j = gi - base, sh = 3 - (uint32_t)x;
+    return base + (j & ((1u << sh) - 1)) * T + (j >> sh);
+}
+
+template <int LOGN>
+struct TwPairsLds {
+    const uint2 *p;
+    __device__ __forceinline__ uint2 operator()(int x, uint32_t gi) const { return p[tw_pair_slot<LOGN>(x, gi)]; }
+};
+
+// Fills the N pairs of TwPairsLds from the global tables w, ws (the N/16
+// threads of the block, thread t); the caller synchronises before use.
+template <int LOGN>
+__device__ __forceinline__ void tw_pairs_fill(uint2 *p, const uint32_t *w, const uint32_t *ws, uint32_t t) {
+    constexpr uint32_t n = 1u << LOGN, T = n / QR;
+#pragma unroll
+    for (uint32_t i = 0; i < QR; ++i) {
+        const uint32_t gi = t + i * T;
+        const int x = gi == 0 ? LOGN : LOGN - 1 - (31 - __clz(gi));   // gi in [N >> (x+1), N >> x)
+        p[gi < T ? gi : tw_pair_slot<LOGN>(x, gi)] = make_uint2(w[gi], ws[gi]);
+    }
+}
+
 // Forward transform of one polynomial held by all N/16 threads of a block
 // (N = 2^LOGN >= 256).  On entry register r of thread t holds element
 // qf_elem(t, r, LOGN - 4) of the natural coefficient order (a residue below
@@ -74,10 +115,10 @@ enum : int {
 // since Shoup's product without its correction lies in [0, 2q) for any
 // 32-bit input).  poly is LDS of N + N/16 words; the first exchange begins
 // with a barrier, so earlier reads of poly by the block are complete before
-// it is overwritten.
-template <int LOGN, int MODE>
-__device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uint32_t *poly,
-                                              const uint32_t *tw, const uint32_t *tws, uint32_t q) {
+// it is overwritten.  tw: a twiddle source (TwGlobal, TwPairsLds).
+template <int LOGN, int MODE, class TW>
+__device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uint32_t *poly, const TW &tw,
+                                              uint32_t q) {
     constexpr uint32_t n = 1u << LOGN;
     uint32_t lo = LOGN - 4;
 #pragma unroll
@@ -96,10 +137,8 @@ __device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uin
         }
         // (the twiddle index stays in the per-register form: written as a
         // thread base plus a constant, the compiler proves the first chunk's
-        // twiddles wave-uniform and reads them with scalar loads, whose wait
-        // counter the LDS exchanges share; the ColTor multiply-accumulate
-        // kernel, which keeps its twiddles in registers across 2 ell
-        // transforms, then took 5.8 ms instead of 3.3 ms)
+        // twiddles wave-uniform and, from global memory, reads them with
+        // scalar loads, whose wait counter the LDS exchanges share)
 #pragma unroll
         for (int x = hi - 1; x >= clo; --x) {
             const uint32_t bit = 1u << (x - (int)lo), mgroups = n >> (x + 1);
@@ -107,17 +146,18 @@ __device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uin
             for (int r = 0; r < QR; ++r) {
                 if (r & bit) continue;
                 const uint32_t gi = mgroups + (qf_elem(t, r, lo) >> (x + 1));
+                const uint2 w2 = tw(x, gi);
                 if (MODE == NTT_WIDE) {
-                    const uint32_t u = v[r], w = mul_shoup_w(v[r | bit], tw[gi], tws[gi], q);
+                    const uint32_t u = v[r], w = mul_shoup_w(v[r | bit], w2.x, w2.y, q);
                     v[r] = add_mod_w(u, w, q);
                     v[r | bit] = sub_mod(u, w, q);
                 } else if (MODE == NTT_GROW) {
                     const uint32_t y = v[r | bit];
-                    const uint32_t tt = y * tw[gi] - __umulhi(y, tws[gi]) * q;
+                    const uint32_t tt = y * w2.x - __umulhi(y, w2.y) * q;
                     v[r | bit] = v[r] + 2 * q - tt;
                     v[r] = v[r] + tt;
                 } else {
-                    qf_bfly(v[r], v[r | bit], tw[gi], tws[gi], q, 2 * q);
+                    qf_bfly(v[r], v[r | bit], w2.x, w2.y, q, 2 * q);
                 }
             }
         }
