@@ -59,6 +59,11 @@ CASES = [
     (256, (synth.PRIMES_W32[0],), 30, 2, 2, 2),
     # three limbs: blocks of 3 x N/16 threads
     (512, Q108[:3], 22, 4, 1, 4),
+    # N = 2048: the forward transform's stage 3 runs in a chunk whose register
+    # bits start at bit 3 (every other N puts it in the last chunk, bits from
+    # 0, or in one from bit 1 or 2); unreduced and lazy butterflies
+    (2048, Q108[:2], 22, 4, 1, 3),
+    (2048, (1073692673,), 16, 2, 2, 2),
 ]
 
 
