@@ -25,8 +25,10 @@
 //   multiply-accumulate one block per (node, limb): for each of the 2*ell
 //                      digit polynomials, the residues mod q_l, the forward
 //                      NTT and the product with the two RGSW components of
-//                      that row, summed in registers; then ct0 is added and
-//                      both output polynomials stored.
+//                      that row, summed in registers (up to N = 4096 the
+//                      limb's twiddles are staged in LDS, and the next digit
+//                      polynomial is loaded during the current transform);
+//                      then ct0 is added and both output polynomials stored.
 // The butterfly and sum forms are chosen per launch from the primes: wide
 // (64-bit intermediates) for any prime of 2^30 or more, lazy below, and
 // unreduced forward butterflies when (1 + 2 logN) q < 2^32; the small-ring
