@@ -29,14 +29,17 @@ __device__ __forceinline__ uint32_t qf_pad(uint32_t e) { return e + (e >> 4); }
 
 // Lazy butterfly (Harvey): inputs and outputs in [0, 4q), which fits 32 bits
 // for q < 2^30.  x is first brought into [0, 2q) (x - 2q wraps above x when
-// x < 2q, so the minimum picks the reduced value); Shoup's product without
-// its final correction lies in [0, 2q) for any 32-bit y.
+// x < 2q, so the minimum picks the reduced value); Shoup's product
+// t = y w - floor(y w' / 2^32) q without its final correction lies in
+// [0, 2q) for any 32-bit y.  It is formed negated, nt = -t mod 2^32, so that
+// x + t = x - nt and x - t + 2q = x + 2q + nt, the latter one three-input
+// add.
 __device__ __forceinline__ void qf_bfly(uint32_t &x, uint32_t &y, uint32_t w, uint32_t ws, uint32_t q,
                                         uint32_t q2) {
     const uint32_t xr = min(x, x - q2);
-    const uint32_t t = y * w - __umulhi(y, ws) * q;
-    x = xr + t;
-    y = xr - t + q2;
+    const uint32_t nt = __umulhi(y, ws) * q - y * w;
+    x = xr - nt;
+    y = xr + q2 + nt;
 }
 
 // [0, 4q) -> [0, q)
@@ -152,10 +155,11 @@ __device__ __forceinline__ void ntt_reg_block(uint32_t (&v)[QR], uint32_t t, uin
                     v[r] = add_mod_w(u, w, q);
                     v[r | bit] = sub_mod(u, w, q);
                 } else if (MODE == NTT_GROW) {
+                    // Shoup's product negated, as in qf_bfly
                     const uint32_t y = v[r | bit];
-                    const uint32_t tt = y * w2.x - __umulhi(y, w2.y) * q;
-                    v[r | bit] = v[r] + 2 * q - tt;
-                    v[r] = v[r] + tt;
+                    const uint32_t nt = __umulhi(y, w2.y) * q - y * w2.x;
+                    v[r | bit] = v[r] + 2 * q + nt;
+                    v[r] = v[r] - nt;
                 } else {
                     qf_bfly(v[r], v[r | bit], w2.x, w2.y, q, 2 * q);
                 }
