@@ -15,7 +15,7 @@
 // exchanges at N = 4096); smaller rings use one LDS stage per barrier with
 // KG polynomials of consecutive k per block (query_ntt_kernel).  On the
 // 2 GiB query of 64 clients (N = 4096, two primes, D0 = 512) the transform
-// takes ~1.2 ms, against ~4.3 ms for the per-polynomial NTT of the DB load
+// takes ~1.15 ms, against ~4.3 ms for the per-polynomial NTT of the DB load
 // and ~7 ms for the one-stage-per-barrier form over 8 polynomials.
 //
 // Writing the MFMA path's digit planes straight from the transform (KG bytes
