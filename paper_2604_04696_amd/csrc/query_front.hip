@@ -124,7 +124,10 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
     uint32_t lo = logn - 4;                          // register bits of the first chunk
     if (live) {
         // any 32-bit coefficient: x - floor(x * floor(2^32/q) / 2^32) * q is
-        // x mod q or x mod q + q, in [0, 2q) as the lazy butterflies allow
+        // x mod q or x mod q + q, in [0, 2q) as the lazy butterflies allow.
+        // The first stage pairs registers r and r + 8, and only its first
+        // operands need the reduction: the second ones go into Shoup's
+        // product, which takes any 32-bit value.
         const uint32_t r1 = pr.r1[l];
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
@@ -132,6 +135,8 @@ query_ntt_reg_kernel(const uint32_t *__restrict__ q, uint32_t *__restrict__ qn, 
             if (WIDE) {   // q >= 2^30: [0, 2q) needs 64 bits; reduce fully (no lazy range)
                 const uint64_t y = (uint64_t)x - (uint64_t)__umulhi(x, r1) * qv;
                 v[r] = (uint32_t)(y >= qv ? y - qv : y);
+            } else if (r & 8) {
+                v[r] = x;
             } else {
                 v[r] = x - __umulhi(x, r1) * qv;
             }
